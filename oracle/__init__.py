@@ -1,0 +1,193 @@
+"""CPU oracle for the flow classify/aggregate path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg import this package; the product library never
+does, and shares no code with it.
+
+Two implementations of one definition:
+  * `brute`  — pure Python, big integers, linear prefix scan (tiny inputs);
+  * `gnm_oracle.c` — plain C with OpenMP over records, exact 128-bit rate,
+    per-length sorted tables probed from the longest length down (full sizes).
+The second is pinned against the first, against a worked example, closed-form
+rate cases and conservation/permutation invariants in the CPU test suite.
+
+Row layout of every result (one row = 8 unsigned 64-bit fields):
+  flows, bytes, packets, duration_ms, bulk_flows, rate_sum_bps,
+  rate_min_bps (2**64-1 when no bulk flow), rate_max_bps.
+Rows are 2*site+dir (dir 0 inbound, 1 outbound) for site 0..S, where S is the
+"no registered site" row, then NODIR = 2*S+2.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+from . import brute  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gnm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, E_INVAL, E_CONFLICT, E_NOMEM = 0, -1, -2, -3
+M64 = (1 << 64) - 1
+FIELDS = ("flows", "bytes", "packets", "duration_ms", "bulk_flows",
+          "rate_sum_bps", "rate_min_bps", "rate_max_bps")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _LIB if os.path.exists(_LIB) else build()
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        L.orc_registry_build.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(P)]
+        L.orc_registry_build.restype = ctypes.c_int
+        L.orc_registry_free.argtypes = [P]
+        L.orc_lookup.argtypes = [P, ctypes.c_uint32]
+        L.orc_lookup.restype = ctypes.c_uint32
+        L.orc_lookup_many.argtypes = [P, P, ctypes.c_uint64, P]
+        L.orc_rate_bps.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+        L.orc_rate_bps.restype = ctypes.c_uint64
+        L.orc_rate_many.argtypes = [P, P, ctypes.c_uint64, P]
+        L.orc_classify_aggregate.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, P,
+                                             ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, P]
+        L.orc_classify_aggregate.restype = ctypes.c_int
+        L.orc_classify_aggregate_windows.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, P, P,
+                                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, P]
+        L.orc_classify_aggregate_windows.restype = ctypes.c_int
+        L.orc_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__({E_INVAL: "invalid argument", E_CONFLICT: "conflicting prefixes",
+                          E_NOMEM: "out of memory"}.get(code, "error %d" % code))
+        self.code = code
+
+
+class Registry:
+    """Oracle-side registry: sites (addr, len, site) plus the local prefix set."""
+
+    def __init__(self, addr, length, site, n_sites: int, local_addr, local_len):
+        self.addr = np.ascontiguousarray(addr, dtype=np.uint32)
+        self.length = np.ascontiguousarray(length, dtype=np.uint32)
+        self.site = np.ascontiguousarray(site, dtype=np.uint32)
+        self.local_addr = np.ascontiguousarray(local_addr, dtype=np.uint32)
+        self.local_len = np.ascontiguousarray(local_len, dtype=np.uint32)
+        self.n_sites = int(n_sites)
+        h = ctypes.c_void_p()
+        rc = lib().orc_registry_build(_p(self.addr), _p(self.length), _p(self.site),
+                                      self.addr.shape[0], self.n_sites, ctypes.byref(h))
+        if rc != OK:
+            raise OracleError(rc)
+        self._h = h
+
+    @classmethod
+    def from_generated(cls, reg) -> "Registry":
+        return cls(reg.addr, reg.length, reg.site, reg.n_sites, reg.local_addr, reg.local_len)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().orc_registry_free(h)
+            self._h = None
+
+    @property
+    def rows(self) -> int:
+        return 2 * self.n_sites + 3
+
+    def lookup(self, ips) -> np.ndarray:
+        ips = np.ascontiguousarray(ips, dtype=np.uint32)
+        out = np.empty(ips.shape[0], dtype=np.uint32)
+        lib().orc_lookup_many(self._h, _p(ips), ips.shape[0], _p(out))
+        return out
+
+    def classify_aggregate(self, rec, bulk_bytes: int = 1_000_000,
+                           threads: int = 0, window_offsets: Optional[np.ndarray] = None) -> np.ndarray:
+        """Rows for each window: uint64[n_windows, rows, 8] (or [rows, 8] for one window)."""
+        f = {k: np.ascontiguousarray(getattr(rec, k)) for k in
+             ("src_ip", "dst_ip", "bytes", "packets", "first_ms", "last_ms")}
+        assert f["bytes"].dtype == np.uint64 and f["src_ip"].dtype == np.uint32
+        off = window_offsets if window_offsets is not None else getattr(rec, "window_offsets", None)
+        if off is None:
+            out = np.empty((self.rows, 8), dtype=np.uint64)
+            rc = lib().orc_classify_aggregate(self._h, _p(self.local_addr), _p(self.local_len),
+                                              self.local_addr.shape[0], _p(f["src_ip"]), _p(f["dst_ip"]),
+                                              _p(f["bytes"]), _p(f["packets"]), _p(f["first_ms"]),
+                                              _p(f["last_ms"]), f["src_ip"].shape[0], bulk_bytes,
+                                              threads, _p(out))
+        else:
+            off = np.ascontiguousarray(off, dtype=np.uint64)
+            nw = off.shape[0] - 1
+            out = np.empty((nw, self.rows, 8), dtype=np.uint64)
+            rc = lib().orc_classify_aggregate_windows(self._h, _p(self.local_addr), _p(self.local_len),
+                                                      self.local_addr.shape[0], _p(f["src_ip"]),
+                                                      _p(f["dst_ip"]), _p(f["bytes"]), _p(f["packets"]),
+                                                      _p(f["first_ms"]), _p(f["last_ms"]), _p(off), nw,
+                                                      bulk_bytes, threads, _p(out))
+        if rc != OK:
+            raise OracleError(rc)
+        return out
+
+
+def rate_bps(nbytes, dur_ms) -> np.ndarray:
+    b = np.ascontiguousarray(nbytes, dtype=np.uint64)
+    d = np.ascontiguousarray(dur_ms, dtype=np.uint32)
+    out = np.empty(b.shape[0], dtype=np.uint64)
+    lib().orc_rate_many(_p(b), _p(d), b.shape[0], _p(out))
+    return out
+
+
+def flags(rows: np.ndarray, n_sites: int, threshold_bps: int = 1_000_000,
+          min_bulk_flows: int = 0) -> np.ndarray:
+    """Sub-optimal flags per site (bit 0 inbound, bit 1 outbound).
+
+    A (site, direction) is flagged when it has at least max(1, min_bulk_flows)
+    bulk flows and its mean per-flow rate floor(rate_sum / bulk_flows) is
+    strictly below the threshold.  The paper warns on a low rate statistic
+    per site (§III.B.1, NetPerf Monitoring Thread; §IV.B); the mean is the
+    reading used here.  Python integers, one (site, direction) at a time.
+    """
+    rows = np.asarray(rows, dtype=np.uint64)
+    single = rows.ndim == 2
+    if single:
+        rows = rows[None]
+    out = np.zeros((rows.shape[0], n_sites), dtype=np.uint8)
+    need = max(1, int(min_bulk_flows))
+    for w in range(rows.shape[0]):
+        for s in range(n_sites):
+            f = 0
+            for d in (0, 1):
+                r = rows[w, 2 * s + d]
+                bulk, rsum = int(r[4]), int(r[5])
+                if bulk >= need and rsum // bulk < threshold_bps:
+                    f |= 1 << d
+            out[w, s] = f
+    return out[0] if single else out
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())

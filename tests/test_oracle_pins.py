@@ -1,0 +1,292 @@
+"""Pins of the CPU oracle against facts independent of it (CPU only).
+
+The oracle is trusted only after these pass: the hand-derived worked example,
+the paper's decimal-unit arithmetic, closed forms of the integer rate,
+brute-force longest-prefix match at every interval boundary, brute-force
+aggregation of random small windows full of edge cases, and conservation /
+permutation / split-merge invariants on generated windows.
+"""
+import numpy as np
+import pytest
+
+import flowgen
+import oracle
+from oracle import brute
+from tests._helpers import (M64, boundary_points, ip, load_golden, random_tiny_registry, soa,
+                            tuples, worked_example)
+
+
+def _oracle_reg(sites, local, n_sites):
+    a = np.array([s[0] for s in sites], dtype=np.uint32)
+    l = np.array([s[1] for s in sites], dtype=np.uint32)
+    s = np.array([s[2] for s in sites], dtype=np.uint32)
+    la = np.array([x[0] for x in local], dtype=np.uint32)
+    ll = np.array([x[1] for x in local], dtype=np.uint32)
+    return oracle.Registry(a, l, s, n_sites, la, ll)
+
+
+# ---------------------------------------------------------------- worked example
+
+def test_worked_example_brute():
+    sites, local, S, recs, exp, g = worked_example()
+    rows = brute.classify_aggregate(sites, local, S, recs, g["bulk_bytes"])
+    assert rows == exp
+    assert [sum(r[k] for r in rows) for k in range(6)] == g["expected_column_totals"]
+    assert brute.flags(rows, S, g["threshold_bps"], 0) == g["expected_flags"]
+
+
+def test_worked_example_c_oracle():
+    sites, local, S, recs, exp, g = worked_example()
+    reg = _oracle_reg(sites, local, S)
+    rows = reg.classify_aggregate(soa(recs), g["bulk_bytes"])
+    assert rows.tolist() == exp
+    assert oracle.flags(rows, S, g["threshold_bps"]).tolist() == g["expected_flags"]
+    for a, site in g["lpm_spot_checks"]:
+        assert int(reg.lookup([ip(a)])[0]) == site
+
+
+def test_worked_example_strict_threshold():
+    # Dropping r8 leaves site 1 outbound with mean exactly 1,000,000: not flagged.
+    sites, local, S, recs, exp, g = worked_example()
+    reg = _oracle_reg(sites, local, S)
+    rows = reg.classify_aggregate(soa(recs[:8] + recs[9:]), g["bulk_bytes"])
+    assert int(rows[3, 5]) // int(rows[3, 4]) == 1_000_000
+    assert oracle.flags(rows, S, g["threshold_bps"]).tolist() == [0, 0, 0]
+    # a minimum bulk-flow count above what the row holds suppresses the flag
+    rows = reg.classify_aggregate(soa(recs), g["bulk_bytes"])
+    assert oracle.flags(rows, S, g["threshold_bps"], min_bulk_flows=3).tolist() == [0, 0, 0]
+    assert oracle.flags(rows, S, g["threshold_bps"], min_bulk_flows=2).tolist() == [0, 2, 0]
+
+
+def test_worked_example_threads_and_order():
+    sites, local, S, recs, exp, g = worked_example()
+    reg = _oracle_reg(sites, local, S)
+    for threads in (1, 3, 8):
+        assert reg.classify_aggregate(soa(recs[::-1]), g["bulk_bytes"], threads=threads).tolist() == exp
+
+
+# ---------------------------------------------------------------- units and rate
+
+def test_paper_decimal_units():
+    u = load_golden("paper_units.json")
+    dgrams = u["records_per_hour"] / 3600 / u["records_per_datagram"]
+    assert round(dgrams) == u["printed_datagrams_per_s"]
+    bps = u["printed_datagrams_per_s"] * u["datagram_bytes"] * 8
+    assert round(bps / 1e6, 2) == u["printed_mbps"]
+    c = u["rate_case"]
+    assert int(oracle.rate_bps([c["bytes"]], [c["duration_ms"]])[0]) == c["rate_bps"] == bps
+    assert brute.rate_bps(c["bytes"], c["duration_ms"]) == c["rate_bps"]
+
+
+RATE_TABLE = [
+    # (bytes, dur_ms, expected) — closed forms worked by hand
+    (1 << 40, 1, 8_796_093_022_208_000),          # 2^40 * 8000
+    (1_000_003, 3, 2_666_674_666),                 # 8,000,024,000 / 3 = ...666.67
+    (1_000_000, 8000, 1_000_000),                  # exact 1 Mbps
+    (1, 8000, 1),                                  # one byte over 8 s = 1 bit/s
+    (1, 8001, 0),                                  # just under 1 bit/s
+    (1 << 63, 1, M64),                             # 2^63 * 8000 > 2^64: saturates
+    (M64, 0xFFFFFFFF, 34_359_738_376_000),         # (2^64-1)/(2^32-1) = 2^32+1, times 8000
+    (0xFFFFFFFF, 0xFFFFFFFF, 8000),
+]
+
+
+@pytest.mark.parametrize("b,d,exp", RATE_TABLE)
+def test_rate_closed_forms(b, d, exp):
+    assert int(oracle.rate_bps([b], [d])[0]) == exp
+    assert brute.rate_bps(b, d) == exp
+
+
+def test_rate_floor_characterisation():
+    # rate is the unique integer q with q*d <= 8000*b < (q+1)*d (unless saturated)
+    rng = np.random.default_rng(7)
+    b = rng.integers(0, 1 << 63, size=4000, dtype=np.uint64) >> rng.integers(0, 63, size=4000).astype(np.uint64)
+    d = rng.integers(1, 1 << 32, size=4000, dtype=np.uint64).astype(np.uint32)
+    d[::7] = 1
+    d[1::7] = 3
+    r = oracle.rate_bps(b, d)
+    for bi, di, ri in zip(b.tolist(), d.tolist(), r.tolist()):
+        if ri == M64:
+            assert 8000 * bi >= M64 * di
+        else:
+            assert ri * di <= 8000 * bi < (ri + 1) * di
+
+
+def test_rate_near_integer_quotients():
+    # 8000*b = k*d - 1 just below an integer: a floating-point floor of the
+    # rounded quotient would return k; the exact answer is k-1.
+    rng = np.random.default_rng(11)
+    cases = []
+    while len(cases) < 2000:
+        d = int(rng.integers(2, 1 << 32))
+        if d % 2 == 0 or d % 5 == 0:
+            continue  # 8000 must be invertible mod d
+        b = (-pow(8000, -1, d)) % d
+        # lift b towards 2^40 (largest bytes of the synthetic workloads)
+        b += d * int(rng.integers(0, max(1, ((1 << 40) - b) // d)))
+        cases.append((b, d))
+    assert len(cases) > 50
+    b = np.array([c[0] for c in cases], dtype=np.uint64)
+    d = np.array([c[1] for c in cases], dtype=np.uint32)
+    r = oracle.rate_bps(b, d).tolist()
+    for (bi, di), ri in zip(cases, r):
+        assert ri == (8000 * bi + 1) // di - 1
+
+
+# ---------------------------------------------------------------- prefix matching
+
+@pytest.mark.parametrize("seed", range(40))
+def test_lpm_matches_brute_force_at_every_boundary(seed):
+    rng = np.random.default_rng(seed)
+    n_sites, sites, local = random_tiny_registry(rng)
+    reg = _oracle_reg(sites, local, n_sites)
+    norm = brute.normalise(sites)
+    pts = boundary_points(sites)
+    got = reg.lookup(np.array(pts, dtype=np.uint32)).tolist()
+    exp = [brute.lpm(norm, p, n_sites) for p in pts]
+    assert got == exp
+
+
+def test_lpm_slash0_and_slash32():
+    sites = [(0, 0, 0), (ip("9.9.9.9"), 32, 1), (ip("9.9.9.0"), 24, 2)]
+    reg = _oracle_reg(sites, [], 3)
+    q = [ip("9.9.9.9"), ip("9.9.9.8"), ip("9.9.9.10"), ip("9.9.8.255"), 0, 0xFFFFFFFF]
+    assert reg.lookup(np.array(q, dtype=np.uint32)).tolist() == [1, 2, 2, 0, 0, 0]
+
+
+def test_registry_normalises_host_bits_and_duplicates():
+    # 10.1.2.3/8 is 10.0.0.0/8; the same prefix twice for one site is fine
+    sites = [(ip("10.1.2.3"), 8, 1), (ip("10.0.0.0"), 8, 1), (ip("10.200.0.0"), 16, 0)]
+    reg = _oracle_reg(sites, [], 2)
+    assert reg.lookup(np.array([ip("10.0.0.1"), ip("10.200.3.4"), ip("11.0.0.0")], dtype=np.uint32)).tolist() == [1, 0, 2]
+
+
+@pytest.mark.parametrize("sites,n_sites,code", [
+    ([(ip("10.0.0.0"), 8, 0), (ip("10.9.9.9"), 8, 1)], 2, oracle.E_CONFLICT),
+    ([(ip("10.0.0.0"), 33, 0)], 1, oracle.E_INVAL),
+    ([(ip("10.0.0.0"), 8, 2)], 2, oracle.E_INVAL),
+])
+def test_registry_errors(sites, n_sites, code):
+    with pytest.raises(oracle.OracleError) as e:
+        _oracle_reg(sites, [], n_sites)
+    assert e.value.code == code
+    if code == oracle.E_CONFLICT or sites[0][1] > 32:
+        with pytest.raises(ValueError):
+            brute.normalise(sites)
+
+
+# ---------------------------------------------------------------- aggregation
+
+def _edge_records(rng, n, sites, local):
+    """Random records biased towards every edge the definition has."""
+    pool = [a for a, _, _ in sites] + [a for a, _ in local] + [0, 0xFFFFFFFF]
+    out = []
+    for _ in range(n):
+        def addr():
+            if pool and rng.random() < 0.7:
+                return (pool[int(rng.integers(0, len(pool)))] + int(rng.integers(-2, 300))) & 0xFFFFFFFF
+            return int(rng.integers(0, 1 << 32))
+        src, dst = addr(), addr()
+        kind = rng.random()
+        if kind < 0.1:
+            b = 1_000_000 + int(rng.integers(-1, 2))           # around the bulk threshold
+        elif kind < 0.15:
+            b = int(rng.integers(1 << 62, 1 << 63)) * 2 + 1    # huge: rate saturates, sums wrap
+        else:
+            b = int(rng.integers(0, 1 << 41))
+        p = int(rng.integers(0, 1 << 32))
+        f = int(rng.integers(0, 1 << 32))
+        dk = rng.random()
+        dur = 0 if dk < 0.1 else (1 if dk < 0.2 else int(rng.integers(0, 1 << 32)))
+        out.append((src, dst, b, p, f, (f + dur) & 0xFFFFFFFF))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_c_oracle_matches_brute_on_edge_windows(seed):
+    rng = np.random.default_rng(100 + seed)
+    n_sites, sites, local = random_tiny_registry(rng, n_local=int(rng.integers(0, 4)))
+    recs = _edge_records(rng, int(rng.integers(0, 120)), sites, local)
+    bulk = int(rng.choice([0, 1_000_000, 1 << 40]))
+    exp = brute.classify_aggregate(sites, local, n_sites, recs, bulk)
+    reg = _oracle_reg(sites, local, n_sites)
+    got = reg.classify_aggregate(soa(recs), bulk, threads=int(rng.integers(1, 5)))
+    assert got.tolist() == exp
+
+
+def test_generated_window_matches_brute_force():
+    reg = flowgen.registry_for(flowgen.PLAIN_SMALL)
+    rec = flowgen.records_for(flowgen.PLAIN_SMALL, n=3000)
+    sites = list(zip(reg.addr.tolist(), reg.length.tolist(), reg.site.tolist()))
+    local = list(zip(reg.local_addr.tolist(), reg.local_len.tolist()))
+    exp = brute.classify_aggregate(sites, local, reg.n_sites, tuples(rec), 1_000_000)
+    got = oracle.Registry.from_generated(reg).classify_aggregate(rec)
+    assert got.tolist() == exp
+
+
+def _combine(a, b):
+    out = a.copy()
+    out[:, :6] = a[:, :6] + b[:, :6]  # uint64 wraps mod 2^64
+    out[:, 6] = np.minimum(a[:, 6], b[:, 6])
+    out[:, 7] = np.maximum(a[:, 7], b[:, 7])
+    return out
+
+
+@pytest.mark.parametrize("workload", [flowgen.PLAIN_SMALL, flowgen.PLAIN_LARGE])
+def test_invariants_on_generated_windows(workload):
+    reg = flowgen.registry_for(workload)
+    rec = flowgen.records_for(workload, reg=reg, n=200_000)
+    o = oracle.Registry.from_generated(reg)
+    rows = o.classify_aggregate(rec)
+    # conservation: every record lands in exactly one row
+    assert int(rows[:, 0].sum()) == rec.n
+    assert int(rows[:, 1].sum(dtype=np.uint64)) == int(rec.bytes.sum(dtype=np.uint64))
+    assert int(rows[:, 2].sum(dtype=np.uint64)) == int(rec.packets.astype(np.uint64).sum())
+    dur = (rec.last_ms.astype(np.int64) - rec.first_ms.astype(np.int64)) % (1 << 32)
+    assert int(rows[:, 3].sum()) == int(dur.sum())
+    bulk = (rec.bytes > 1_000_000) & (dur > 0)
+    assert int(rows[:, 4].sum()) == int(bulk.sum())
+    rates = oracle.rate_bps(rec.bytes[bulk], dur[bulk].astype(np.uint32))
+    assert int(rows[:, 5].sum(dtype=np.uint64)) == int(rates.sum(dtype=np.uint64))
+    assert int(rows[:, 6].min()) == int(rates.min()) and int(rows[:, 7].max()) == int(rates.max())
+    # rows without bulk flows keep the min sentinel and a zero max
+    nb = rows[:, 4] == 0
+    assert (rows[nb, 6] == np.uint64(M64)).all() and (rows[nb, 7] == 0).all()
+    # permutation invariance
+    perm = flowgen.permuted(rec, np.random.default_rng(5))
+    assert (o.classify_aggregate(perm) == rows).all()
+    # split / merge
+    k = 77_777
+    a = o.classify_aggregate(rec.slice(0, k))
+    b = o.classify_aggregate(rec.slice(k, rec.n))
+    assert (_combine(a, b) == rows).all()
+    # direction: the NODIR row holds exactly the both-or-neither-local records
+    def is_local(x):
+        m = np.zeros(x.shape[0], bool)
+        for la, ll in zip(reg.local_addr.tolist(), reg.local_len.tolist()):
+            mask = (0xFFFFFFFF << (32 - ll)) & 0xFFFFFFFF
+            m |= (x & np.uint32(mask)) == np.uint32(la & mask)
+        return m
+    ls, ld = is_local(rec.src_ip), is_local(rec.dst_ip)
+    assert int(rows[-1, 0]) == int((ls == ld).sum())
+    assert int(rows[0:-1:2, 0].sum()) == int((~ls & ld).sum())   # inbound rows
+    assert int(rows[1:-1:2, 0].sum()) == int((ls & ~ld).sum())   # outbound rows
+
+
+def test_windows_equal_window_by_window():
+    reg = flowgen.registry_for(flowgen.PLAIN_SMALL)
+    rec = flowgen.records_for(flowgen.BATCHED, reg=reg, n=400_000)
+    o = oracle.Registry.from_generated(reg)
+    allw = o.classify_aggregate(rec)
+    assert allw.shape[0] == rec.n_windows == 256
+    for w in (0, 1, 100, 255):
+        assert (o.classify_aggregate(rec.window(w)) == allw[w]).all()
+
+
+def test_generator_is_deterministic():
+    a = flowgen.records_for(flowgen.PLAIN_SMALL, n=5000)
+    b = flowgen.records_for(flowgen.PLAIN_SMALL, n=5000)
+    for f in flowgen.Records.FIELDS:
+        assert (getattr(a, f) == getattr(b, f)).all()
+    c = flowgen.records_for(flowgen.PLAIN_SMALL, n=5000, stream=1)
+    assert not (a.src_ip == c.src_ip).all()
