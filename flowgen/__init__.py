@@ -88,6 +88,11 @@ class Records:
     def slice(self, lo: int, hi: int) -> "Records":
         return Records(*(getattr(self, f)[lo:hi] for f in self.FIELDS))
 
+    def copy(self) -> "Records":
+        r = Records(*(np.array(getattr(self, f)) for f in self.FIELDS))
+        r.window_offsets = None if self.window_offsets is None else np.array(self.window_offsets)
+        return r
+
     def window(self, w: int) -> "Records":
         off = self.window_offsets
         return self.slice(int(off[w]), int(off[w + 1]))

@@ -1,0 +1,254 @@
+/*
+ * gnm.h — C ABI of libgnm: classification of NetFlow-style flow records by
+ * longest-prefix match against a registry of collaboration-site subnets, and
+ * reduction of the classified records into per-site, per-direction integer
+ * totals and bulk-transfer rate statistics, on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: G-NetMon (Wu, DeMar, Holmgren, Singh, Pordes; arXiv 1108.1785).
+ *   - registered scientific subnets identify transfers between the local site
+ *     and collaboration sites (§III.B.1, Site Registration Thread);
+ *   - a read-only lookup structure is built from the registry and rebuilt
+ *     from scratch on any change (§III.B.2, Catalog Kernel);
+ *   - one pass over the flow records assigns each record to a site from its
+ *     source or destination address and derives a transfer rate from its
+ *     bytes and first/last packet timestamps; per-site statistics are
+ *     accumulated with atomic updates (§III.B.2, TransRate Kernel);
+ *   - sites whose rate statistic falls below a standard are warned about
+ *     (§III.B.1, NetPerf Monitoring Thread; §IV.B).
+ *
+ * Definition computed (bit-exact, integer only).  For each record in a window:
+ *   mask(L)      = 0 for L = 0, else the top L bits set.
+ *   local(ip)    = ip lies in any local prefix.
+ *   direction    : exactly one endpoint local; inbound (0) when the destination
+ *                  is local (remote = source), outbound (1) when the source is
+ *                  local (remote = destination).  Otherwise the record goes to
+ *                  the NODIR row.
+ *   site         = site of the longest registered prefix containing the remote
+ *                  address, or n_sites ("no registered site") when none does.
+ *   row          = 2*site + direction, or NODIR = 2*n_sites + 2.
+ *   dur          = (last_ms - first_ms) mod 2^32.
+ *   bulk         = bytes > bulk_bytes and dur > 0.
+ *   rate         = min(floor(bytes * 8000 / dur), 2^64 - 1)   [bit/s, decimal]
+ *   row.flows += 1; row.bytes += bytes; row.packets += packets;
+ *   row.duration_ms += dur; if bulk: row.bulk_flows += 1,
+ *   row.rate_sum_bps += rate, row.rate_min_bps = min(.., rate),
+ *   row.rate_max_bps = max(.., rate).
+ * Every sum is modulo 2^64; an untouched row is all zero except
+ * rate_min_bps = 2^64-1.  The result is a unique integer table: it does not
+ * depend on record order, launch shape or thread timing.
+ *
+ * Conventions for every entry point:
+ *   - Return GNM_OK (0) or a negative GNM_E_* code; nothing is thrown across
+ *     the ABI.  After GNM_E_HIP, gnm_last_error() names the HIP error.
+ *   - Device pointers are caller-owned device memory (hipMalloc or any
+ *     allocator of the same device); the library never frees them.
+ *   - Work is enqueued on the caller's stream (NULL = the null stream) and the
+ *     call returns; results are valid once that stream has synchronised, and
+ *     inputs must stay alive and unmodified until then.
+ *   - Addresses are host-order uint32 with the first octet in the most
+ *     significant byte (10.0.0.1 = 0x0A000001).
+ */
+#ifndef GNM_H
+#define GNM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GNM_OK 0
+#define GNM_E_INVAL (-1)       /* null pointer, length > 32, site >= n_sites, bad sizes */
+#define GNM_E_CONFLICT (-2)    /* one (network, length) registered to two sites */
+#define GNM_E_NOMEM (-3)       /* host or device allocation failed */
+#define GNM_E_HIP (-4)         /* a HIP runtime call failed; see gnm_last_error() */
+#define GNM_E_UNSUPPORTED (-5) /* e.g. a host-only registry passed to a device call */
+
+/* One CIDR prefix.  For the site registry, `site` is the collaboration-site id
+ * in [0, n_sites); for the local set it is ignored.  Host bits of `addr`
+ * below the prefix length are ignored (the prefix is normalised). */
+typedef struct {
+  uint32_t addr;
+  uint32_t len; /* 0..32 */
+  uint32_t site;
+} gnm_prefix;
+
+/* A run of flow records in structure-of-arrays form, all device pointers of
+ * n elements.  Ports and protocol belong to the record format but are not
+ * read by this path and may be NULL. */
+typedef struct {
+  const uint32_t *src_ip;
+  const uint32_t *dst_ip;
+  const uint16_t *src_port; /* may be NULL (not read) */
+  const uint16_t *dst_port; /* may be NULL (not read) */
+  const uint8_t *proto;     /* may be NULL (not read) */
+  const uint64_t *bytes;
+  const uint32_t *packets;
+  const uint32_t *first_ms; /* router uptime at the first packet, ms */
+  const uint32_t *last_ms;  /* router uptime at the last packet, ms */
+  uint64_t n;
+} gnm_records;
+
+/* One accumulator row (64 bytes).  The table of one window holds
+ * gnm_acc_rows(reg) rows: 2*site+dir for site in [0, n_sites] (site n_sites
+ * = no registered site), then NODIR. */
+typedef struct {
+  uint64_t flows;
+  uint64_t bytes;
+  uint64_t packets;
+  uint64_t duration_ms;
+  uint64_t bulk_flows;
+  uint64_t rate_sum_bps;
+  uint64_t rate_min_bps; /* 2^64-1 while the row has no bulk flow */
+  uint64_t rate_max_bps;
+} gnm_acc;
+
+#define GNM_ACCUMULATE 0x1u /* gnm_params.flags: add into acc instead of initialising it */
+
+/* Per-call parameters.  Zero-initialise and set what you need;
+ * gnm_params_default() gives bulk_bytes = 1,000,000 and automatic tuning. */
+typedef struct {
+  uint64_t bulk_bytes;         /* bulk iff bytes > bulk_bytes and dur > 0 */
+  uint32_t flags;              /* GNM_ACCUMULATE */
+  uint32_t records_per_thread; /* 0 = automatic; else 1, 2, 4 or 8 */
+  uint32_t grid_blocks;        /* 0 = automatic; else workgroups of the launch */
+  uint32_t reserved;
+} gnm_params;
+
+#define GNM_REG_HOST_ONLY 0x1u /* gnm_registry_opts.flags: build host structure only */
+
+/* Registry build options (NULL = defaults). */
+typedef struct {
+  uint32_t flags;          /* GNM_REG_HOST_ONLY: no device upload (inspection only) */
+  uint32_t root_bits;      /* 0 = automatic; else 8..15 bits indexed by the LDS-resident top level */
+  uint32_t list_max;       /* 0 = automatic; else 2..64 intervals searched per leaf */
+  uint32_t lds_bytes;      /* 0 = automatic; LDS budget of the lookup structure */
+} gnm_registry_opts;
+
+/* Facts about a built registry. */
+typedef struct {
+  uint64_t n_prefixes_in;   /* prefixes passed in */
+  uint64_t n_prefixes;      /* distinct normalised prefixes */
+  uint64_t n_host_bits;     /* prefixes that had host bits set (cleared) */
+  uint64_t n_duplicates;    /* exact duplicates for the same site (dropped) */
+  uint64_t n_intervals;     /* maximal address intervals with one answer */
+  uint64_t n_nodes;         /* inner direct-index nodes below the root */
+  uint64_t n_list_entries;  /* interval starts held in leaf lists */
+  uint64_t device_bytes;    /* device memory held by the registry */
+  uint32_t n_sites;
+  uint32_t n_local_ranges;  /* disjoint address ranges of the local set */
+  uint32_t root_bits;
+  uint32_t list_max;
+  uint32_t lists_in_lds;    /* 1 if leaf lists are staged into LDS */
+  uint32_t acc_in_lds;      /* 1 if the whole per-block accumulator table fits LDS */
+  uint32_t lds_bytes;       /* LDS a classify workgroup uses */
+  uint32_t reserved;
+} gnm_registry_info;
+
+typedef struct gnm_registry gnm_registry; /* opaque, immutable after build */
+
+/*
+ * gnm_registry_build — §III.B.1 (Site Registration Thread) and §III.B.2
+ * (Catalog Kernel: a read-only lookup structure, rebuilt from scratch).
+ *   sites[n_prefixes]  host array of site prefixes (site < n_sites).
+ *   n_sites            number of collaboration sites (1 .. 2^28).
+ *   local[n_local]     host array of local-site prefixes (site ignored);
+ *                      n_local may be 0 (then every record is NODIR).
+ *   opts               NULL or build options.
+ *   stream             stream for the device upload; the call synchronises it
+ *                      before returning (registry builds are not on the hot path).
+ *   out                receives the handle; free it with gnm_registry_free.
+ * Host bits are cleared; duplicates for one site are merged; the same
+ * (network, length) for two sites is GNM_E_CONFLICT.  The handle is immutable
+ * and may be shared by concurrent calls on any streams of its device.
+ */
+int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, uint32_t n_sites,
+                       const gnm_prefix *local, uint32_t n_local,
+                       const gnm_registry_opts *opts, hipStream_t stream,
+                       gnm_registry **out);
+
+/* Free a registry (NULL is a no-op).  The caller must ensure no enqueued work
+ * still uses it (synchronise the streams that used it first). */
+int gnm_registry_free(gnm_registry *reg);
+
+/* Describe a registry.  Host only. */
+int gnm_registry_info_get(const gnm_registry *reg, gnm_registry_info *info);
+
+/* Rows per window table: 2*(n_sites+1) + 1.  0 for a NULL registry. */
+uint64_t gnm_acc_rows(const gnm_registry *reg);
+
+/*
+ * gnm_registry_lookup_host — walk the registry's lookup structure on the host
+ * for n host addresses: site_out[i] = longest-match site (n_sites if none),
+ * local_out[i] = 1 if the address is local (either output may be NULL).
+ * For validating a built structure; the classify path never calls it.
+ */
+int gnm_registry_lookup_host(const gnm_registry *reg, const uint32_t *ip, uint64_t n,
+                             uint32_t *site_out, uint8_t *local_out);
+
+/* Defaults: bulk_bytes 1,000,000, no flags, automatic launch shape. */
+gnm_params gnm_params_default(void);
+
+/*
+ * gnm_classify_aggregate — §III.B.2 (TransRate Kernel) with the definition
+ * above, for one or many windows in one launch.
+ *   reg             registry built with a device upload.
+ *   rec             device SoA records; rec->n records.
+ *   window_offsets  NULL: one window [0, rec->n).  Otherwise a DEVICE array of
+ *                   n_windows+1 uint64 with offsets[0] = 0, non-decreasing,
+ *                   offsets[n_windows] = rec->n; window w is
+ *                   [offsets[w], offsets[w+1]) (empty windows allowed).
+ *                   Offsets outside [0, rec->n] are clamped; records are never
+ *                   read out of bounds, but inconsistent offsets give
+ *                   unspecified (not undefined) table contents.
+ *   n_windows       >= 1 (must be 1 when window_offsets is NULL).
+ *   p               NULL = gnm_params_default().
+ *   acc             DEVICE array of n_windows * gnm_acc_rows(reg) rows,
+ *                   window-major.  Initialised by the call unless
+ *                   p->flags has GNM_ACCUMULATE (then added into).
+ *   stream          the caller's stream.
+ * Enqueues an initialisation kernel (unless accumulating) and one classify
+ * kernel; with several windows the launch is persistent and each workgroup
+ * walks a balanced contiguous slice of all records, flushing its LDS table at
+ * window changes.  Errors: GNM_E_INVAL (null pointers, n_windows = 0,
+ * offsets NULL with n_windows > 1, records_per_thread not 0/1/2/4/8),
+ * GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
+ */
+int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
+                           const uint64_t *window_offsets, uint32_t n_windows,
+                           const gnm_params *p, gnm_acc *acc, hipStream_t stream);
+
+/*
+ * gnm_flag_suboptimal — §III.B.1 (NetPerf Monitoring Thread) and §IV.B:
+ * warn about sites whose transfer rate falls below a standard.
+ *   acc             DEVICE tables of n_windows windows (as produced above).
+ *   threshold_bps   e.g. 1,000,000 (1 Mbps, the paper's standard).
+ *   min_bulk_flows  a (site, direction) needs at least max(1, min_bulk_flows)
+ *                   bulk flows to be judged.
+ *   flags           DEVICE array of n_windows * n_sites bytes, window-major:
+ *                   bit 0 = inbound flagged, bit 1 = outbound flagged, where
+ *                   flagged means floor(rate_sum_bps / bulk_flows) <
+ *                   threshold_bps (strict).  The "no site" and NODIR rows are
+ *                   never flagged.
+ * Errors: GNM_E_INVAL (null pointers, n_windows = 0), GNM_E_HIP.
+ */
+int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_windows,
+                        uint64_t threshold_bps, uint64_t min_bulk_flows, uint8_t *flags,
+                        hipStream_t stream);
+
+/* Static description of an error code. */
+const char *gnm_strerror(int code);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char *gnm_last_error(void);
+
+/* Library version string. */
+const char *gnm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNM_H */

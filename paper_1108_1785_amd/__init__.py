@@ -1,0 +1,272 @@
+"""Python binding of libgnm (ctypes): argument marshalling only.
+
+Every step of the classify/aggregate path runs in the library's HIP kernels
+for gfx950; this module converts torch device tensors to raw pointers and the
+current torch stream to a HIP stream handle.  There is no fallback: if
+libgnm.so has not been built, importing works but every call raises.
+
+Function names follow the C ABI in include/gnm.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgnm.so")
+
+GNM_OK = 0
+GNM_E_INVAL = -1
+GNM_E_CONFLICT = -2
+GNM_E_NOMEM = -3
+GNM_E_HIP = -4
+GNM_E_UNSUPPORTED = -5
+GNM_ACCUMULATE = 0x1
+GNM_REG_HOST_ONLY = 0x1
+
+ACC_FIELDS = ("flows", "bytes", "packets", "duration_ms", "bulk_flows",
+              "rate_sum_bps", "rate_min_bps", "rate_max_bps")
+RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms": 4, "last_ms": 4}
+
+# symbols declared in include/gnm.h
+EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
+           "gnm_registry_lookup_host", "gnm_params_default", "gnm_classify_aggregate",
+           "gnm_flag_suboptimal", "gnm_strerror", "gnm_last_error", "gnm_version")
+
+
+class Prefix(ctypes.Structure):
+    _fields_ = [("addr", ctypes.c_uint32), ("len", ctypes.c_uint32), ("site", ctypes.c_uint32)]
+
+
+class RecordsC(ctypes.Structure):
+    _fields_ = [("src_ip", ctypes.c_void_p), ("dst_ip", ctypes.c_void_p),
+                ("src_port", ctypes.c_void_p), ("dst_port", ctypes.c_void_p), ("proto", ctypes.c_void_p),
+                ("bytes", ctypes.c_void_p), ("packets", ctypes.c_void_p),
+                ("first_ms", ctypes.c_void_p), ("last_ms", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("bulk_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("records_per_thread", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class RegistryOpts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("root_bits", ctypes.c_uint32),
+                ("list_max", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32)]
+
+
+class RegistryInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("n_prefixes_in", "n_prefixes", "n_host_bits", "n_duplicates",
+                                               "n_intervals", "n_nodes", "n_list_entries", "device_bytes")] + \
+               [(n, ctypes.c_uint32) for n in ("n_sites", "n_local_ranges", "root_bits", "list_max",
+                                               "lists_in_lds", "acc_in_lds", "lds_bytes", "reserved")]
+
+    def as_dict(self) -> Dict[str, int]:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
+class GnmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = _lib_or_none()
+        msg = lib.gnm_strerror(code).decode() if lib else str(code)
+        detail = lib.gnm_last_error().decode() if lib else ""
+        super().__init__("%s: %s%s" % (where, msg, (" (%s)" % detail) if detail else ""))
+        self.code = code
+
+
+_lib = None
+
+
+def _lib_or_none():
+    return _lib
+
+
+def lib():
+    """The loaded libgnm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgnm.so is not built (run __graft_entry__.build()); "
+                               "there is no non-HIP implementation of this path")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.gnm_registry_build.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, P, ctypes.c_uint32, P, P,
+                                         ctypes.POINTER(P)]
+        L.gnm_registry_build.restype = ctypes.c_int
+        L.gnm_registry_free.argtypes = [P]
+        L.gnm_registry_free.restype = ctypes.c_int
+        L.gnm_registry_info_get.argtypes = [P, ctypes.POINTER(RegistryInfo)]
+        L.gnm_registry_info_get.restype = ctypes.c_int
+        L.gnm_acc_rows.argtypes = [P]
+        L.gnm_acc_rows.restype = ctypes.c_uint64
+        L.gnm_registry_lookup_host.argtypes = [P, P, ctypes.c_uint64, P, P]
+        L.gnm_registry_lookup_host.restype = ctypes.c_int
+        L.gnm_params_default.argtypes = []
+        L.gnm_params_default.restype = Params
+        L.gnm_classify_aggregate.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32,
+                                             ctypes.POINTER(Params), P, P]
+        L.gnm_classify_aggregate.restype = ctypes.c_int
+        L.gnm_flag_suboptimal.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P]
+        L.gnm_flag_suboptimal.restype = ctypes.c_int
+        L.gnm_strerror.argtypes = [ctypes.c_int]
+        L.gnm_strerror.restype = ctypes.c_char_p
+        L.gnm_last_error.argtypes = []
+        L.gnm_last_error.restype = ctypes.c_char_p
+        L.gnm_version.argtypes = []
+        L.gnm_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != GNM_OK:
+        raise GnmError(rc, where)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    h = getattr(stream, "cuda_stream", stream)
+    return ctypes.c_void_p(int(h) if h else 0)
+
+
+def _prefix_array(addr, length, site=None):
+    addr = np.asarray(addr, dtype=np.uint64).reshape(-1)
+    length = np.asarray(length, dtype=np.uint64).reshape(-1)
+    n = addr.shape[0]
+    arr = (Prefix * max(n, 1))()
+    site = np.zeros(n, dtype=np.uint64) if site is None else np.asarray(site, dtype=np.uint64).reshape(-1)
+    for i, (a, l, s) in enumerate(zip(addr.tolist(), length.tolist(), site.tolist())):
+        arr[i].addr, arr[i].len, arr[i].site = a, l, s
+    return arr, n
+
+
+class Registry:
+    """gnm_registry_build / gnm_registry_free over host prefix arrays."""
+
+    def __init__(self, addr, length, site, n_sites: int, local_addr=(), local_len=(),
+                 root_bits: int = 0, list_max: int = 0, lds_bytes: int = 0,
+                 host_only: bool = False, stream=None):
+        L = lib()
+        sites, n = _prefix_array(addr, length, site)
+        local, nl = _prefix_array(local_addr, local_len)
+        opts = RegistryOpts(GNM_REG_HOST_ONLY if host_only else 0, root_bits, list_max, lds_bytes)
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(0) if host_only else _stream_handle(stream)
+        _check(L.gnm_registry_build(sites, n, int(n_sites), local, nl, ctypes.byref(opts), st,
+                                    ctypes.byref(h)), "gnm_registry_build")
+        self._h = h
+        self.n_sites = int(n_sites)
+        self.host_only = host_only
+
+    @classmethod
+    def from_generated(cls, reg, **kw) -> "Registry":
+        return cls(reg.addr, reg.length, reg.site, reg.n_sites, reg.local_addr, reg.local_len, **kw)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise RuntimeError("registry is closed")
+        return self._h
+
+    @property
+    def rows(self) -> int:
+        return int(lib().gnm_acc_rows(self.handle))
+
+    def info(self) -> Dict[str, int]:
+        i = RegistryInfo()
+        _check(lib().gnm_registry_info_get(self.handle, ctypes.byref(i)), "gnm_registry_info_get")
+        return i.as_dict()
+
+    def lookup_host(self, ips):
+        ips = np.ascontiguousarray(ips, dtype=np.uint32)
+        site = np.empty(ips.shape[0], dtype=np.uint32)
+        loc = np.empty(ips.shape[0], dtype=np.uint8)
+        _check(lib().gnm_registry_lookup_host(self.handle, ips.ctypes.data, ips.shape[0], site.ctypes.data,
+                                              loc.ctypes.data), "gnm_registry_lookup_host")
+        return site, loc.astype(bool)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _check(lib().gnm_registry_free(self._h), "gnm_registry_free")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t, elem: int, n: int, name: str, device=None) -> int:
+    if t is None:
+        raise ValueError("record field %s is required" % name)
+    if t.element_size() != elem:
+        raise ValueError("record field %s must have %d-byte elements" % (name, elem))
+    if not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+        raise ValueError("record field %s must be a contiguous device tensor of >= %d elements" % (name, n))
+    return t.data_ptr()
+
+
+def records_struct(rec: Dict[str, "object"], n: Optional[int] = None) -> RecordsC:
+    """SoA device tensors (src_ip, dst_ip, bytes, packets, first_ms, last_ms) -> gnm_records."""
+    if n is None:
+        n = int(rec["src_ip"].numel())
+    c = RecordsC()
+    for f, elem in RECORD_FIELDS.items():
+        setattr(c, f, _ptr(rec[f], elem, n, f))
+    c.n = n
+    return c
+
+
+def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_per_thread: int = 0,
+                grid_blocks: int = 0) -> Params:
+    p = lib().gnm_params_default()
+    p.bulk_bytes = int(bulk_bytes)
+    p.flags = GNM_ACCUMULATE if accumulate else 0
+    p.records_per_thread = int(records_per_thread)
+    p.grid_blocks = int(grid_blocks)
+    return p
+
+
+def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1,
+                       bulk_bytes: int = 1_000_000, accumulate: bool = False,
+                       records_per_thread: int = 0, grid_blocks: int = 0, stream=None,
+                       n: Optional[int] = None) -> None:
+    """gnm_classify_aggregate: acc is a device tensor of n_windows*rows*8 64-bit words."""
+    c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
+    if acc.element_size() * acc.numel() < n_windows * reg.rows * 64 or not acc.is_cuda:
+        raise ValueError("acc must be a device tensor of n_windows * rows * 64 bytes")
+    off = 0
+    if window_offsets is not None:
+        if window_offsets.element_size() != 8 or window_offsets.numel() < n_windows + 1 or not window_offsets.is_cuda:
+            raise ValueError("window_offsets must be a device tensor of n_windows+1 64-bit offsets")
+        off = window_offsets.data_ptr()
+    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks)
+    _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
+                                        ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
+                                        _stream_handle(stream)), "gnm_classify_aggregate")
+
+
+def flag_suboptimal(reg: Registry, acc, n_windows: int, flags, threshold_bps: int = 1_000_000,
+                    min_bulk_flows: int = 0, stream=None) -> None:
+    """gnm_flag_suboptimal: flags is a device uint8 tensor of n_windows*n_sites bytes."""
+    if flags.element_size() != 1 or flags.numel() < n_windows * reg.n_sites or not flags.is_cuda:
+        raise ValueError("flags must be a device uint8 tensor of n_windows * n_sites bytes")
+    _check(lib().gnm_flag_suboptimal(reg.handle, ctypes.c_void_p(acc.data_ptr()), int(n_windows),
+                                     int(threshold_bps), int(min_bulk_flows), ctypes.c_void_p(flags.data_ptr()),
+                                     _stream_handle(stream)), "gnm_flag_suboptimal")
+
+
+def version() -> str:
+    return lib().gnm_version().decode()
+
+
+def acc_to_numpy(acc) -> np.ndarray:
+    """Device acc tensor (int64 words) -> host uint64 array [..., rows, 8]."""
+    return acc.detach().cpu().numpy().view(np.uint64)

@@ -1,0 +1,407 @@
+// Host-side registry builder: validation, normalisation, longest-prefix-match
+// resolution into disjoint address intervals, and the direct-indexed trie
+// layout uploaded to the device.
+//
+// §III.B.1 (Site Registration Thread): registered subnets identify transfers
+// between the local site and its collaboration sites.  §III.B.2 (Catalog
+// Kernel): the lookup structure is read-only on the device and rebuilt from
+// scratch on any change.  The paper expands every subnet into /24 hash
+// entries; here any length /0../32 is supported and overlapping prefixes
+// resolve to the longest one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "registry.h"
+
+namespace gnm {
+
+thread_local std::string g_last_error;
+void set_last_error(const std::string &s) { g_last_error = s; }
+
+namespace {
+
+inline uint32_t mask_of(uint32_t len) { return len == 0 ? 0u : (0xFFFFFFFFu << (32u - len)); }
+
+struct Pfx {
+  uint32_t addr, len, site;
+};
+
+// Sorted by start address, then shorter (enclosing) first.
+bool pfx_less(const Pfx &a, const Pfx &b) {
+  if (a.addr != b.addr) return a.addr < b.addr;
+  if (a.len != b.len) return a.len < b.len;
+  return a.site < b.site;
+}
+
+struct Interval {
+  uint32_t start;
+  uint32_t site;
+};
+
+// Append an interval [x, ...) answering `site`, keeping the list minimal:
+// a zero-length predecessor is replaced and equal neighbours are merged.
+void emit(std::vector<Interval> &out, uint64_t x, uint32_t site) {
+  if (!out.empty() && out.back().start == (uint32_t)x) {
+    out.back().site = site;
+    if (out.size() >= 2 && out[out.size() - 2].site == site) out.pop_back();
+    return;
+  }
+  if (!out.empty() && out.back().site == site) return;
+  out.push_back({(uint32_t)x, site});
+}
+
+// Resolve prefixes (normalised, distinct, sorted by pfx_less) into the
+// maximal intervals of the longest-match function.  Prefixes are either
+// nested or disjoint, so a stack of enclosing prefixes gives the answer of
+// every address between consecutive prefix boundaries.
+std::vector<Interval> resolve(const std::vector<Pfx> &p, uint32_t none) {
+  struct Open {
+    uint64_t end;  // inclusive
+    uint32_t site;
+  };
+  std::vector<Interval> out;
+  std::vector<Open> stack;
+  uint64_t cur = 0;  // first address not yet emitted
+  for (const Pfx &q : p) {
+    const uint64_t start = q.addr;
+    while (!stack.empty() && stack.back().end < start) {
+      const Open top = stack.back();
+      stack.pop_back();
+      if (cur <= top.end) {
+        emit(out, cur, top.site);
+        cur = top.end + 1;
+      }
+    }
+    if (cur < start) {
+      emit(out, cur, stack.empty() ? none : stack.back().site);
+      cur = start;
+    }
+    stack.push_back({start + ((uint64_t)1 << (32 - q.len)) - 1, q.site});
+  }
+  while (!stack.empty()) {
+    const Open top = stack.back();
+    stack.pop_back();
+    if (cur <= top.end) {
+      emit(out, cur, top.site);
+      cur = top.end + 1;
+    }
+  }
+  if (cur <= 0xFFFFFFFFull) emit(out, cur, none);
+  if (out.empty() || out.front().start != 0) out.insert(out.begin(), {0u, none});
+  return out;
+}
+
+struct Layout {
+  const std::vector<Interval> *iv;
+  uint32_t list_max;
+  std::vector<uint32_t> nodes, keys, vals;
+  bool overflow = false;
+
+  // index of the interval containing address a
+  size_t find(uint64_t a) const {
+    const auto &v = *iv;
+    size_t lo = 0, hi = v.size();  // v[0].start == 0 <= a
+    while (hi - lo > 1) {
+      size_t mid = (lo + hi) / 2;
+      if ((uint64_t)v[mid].start <= a) lo = mid; else hi = mid;
+    }
+    return lo;
+  }
+
+  // Entry for the cell [lo, lo + 2^shift).
+  uint32_t cell(uint64_t lo, uint32_t shift) {
+    const uint64_t hi = lo + ((uint64_t)1 << shift) - 1;  // inclusive
+    const size_t i0 = find(lo), i1 = find(hi);
+    const size_t count = i1 - i0 + 1;
+    const auto &v = *iv;
+    if (count == 1) return make_leaf(v[i0].site);
+    if (count <= list_max) {
+      const size_t off = keys.size();
+      if (off + count > kListOffsetMask + 1ull) { overflow = true; return make_leaf(0); }
+      keys.push_back((uint32_t)lo);
+      vals.push_back(v[i0].site);
+      for (size_t j = i0 + 1; j <= i1; ++j) {
+        keys.push_back(v[j].start);
+        vals.push_back(v[j].site);
+      }
+      return make_list((uint32_t)off, (uint32_t)count);
+    }
+    const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
+    const uint32_t stride = shift - ns;
+    const size_t base = nodes.size();
+    if (base + ((size_t)1 << stride) > kPayloadMask) { overflow = true; return make_leaf(0); }
+    nodes.resize(base + ((size_t)1 << stride));
+    for (uint64_t c = 0; c < ((uint64_t)1 << stride); ++c) {
+      const uint32_t e = cell(lo + (c << ns), ns);
+      nodes[base + c] = e;
+    }
+    return make_node((uint32_t)base);
+  }
+};
+
+int fail(int code, const char *msg) {
+  set_last_error(msg);
+  return code;
+}
+
+}  // namespace
+
+// Walk of the host copy; mirrors the device walk in kernels.hip.
+uint32_t host_lookup(const gnm_registry *r, uint32_t ip) {
+  uint32_t shift = 32u - r->root_bits;
+  uint32_t e = r->root[ip >> shift];
+  while ((e >> kKindShift) == kKindNode) {
+    const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
+    const uint32_t idx = (ip >> ns) & ((1u << (shift - ns)) - 1u);
+    e = r->nodes[(e & kPayloadMask) + idx];
+    shift = ns;
+  }
+  if ((e >> kKindShift) == kKindLeaf) return e & kPayloadMask;
+  const uint32_t off = e & kListOffsetMask;
+  uint32_t len = ((e >> kListOffsetBits) & 63u) + 1u;
+  uint32_t lo = 0;
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+    if (r->keys[off + lo + half] <= ip) lo += half;
+    len -= half;
+  }
+  return r->vals[off + lo];
+}
+
+bool host_is_local(const gnm_registry *r, uint32_t ip) {
+  for (size_t j = 0; j < r->local_lo.size(); ++j)
+    if (ip - r->local_lo[j] <= r->local_hi[j] - r->local_lo[j]) return true;
+  return false;
+}
+
+// LDS plan for a classify workgroup: root, then (if they fit) the leaf lists,
+// then (if it fits) the accumulator table.
+void plan_lds(gnm_registry *r, uint32_t lds_budget) {
+  const uint64_t root_b = 4ull << r->root_bits;
+  const uint64_t list_b = 4ull * r->keys.size();
+  const uint64_t acc_b = 8ull * kAccFields * r->rows();
+  uint64_t used = root_b;
+  r->acc_in_lds = used + acc_b <= lds_budget;
+  if (r->acc_in_lds) used += acc_b;
+  r->lists_in_lds = used + 2 * list_b <= lds_budget;
+  // layout order: root | acc | keys | vals  (acc 8-byte aligned right after root)
+  r->lds_off_acc = (uint32_t)root_b;
+  uint64_t off = root_b + (r->acc_in_lds ? acc_b : 0);
+  r->lds_off_keys = (uint32_t)off;
+  r->lds_off_vals = (uint32_t)(off + (r->lists_in_lds ? list_b : 0));
+  r->lds_bytes = (uint32_t)(off + (r->lists_in_lds ? 2 * list_b : 0));
+}
+
+}  // namespace gnm
+
+using namespace gnm;
+
+extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, uint32_t n_sites,
+                                  const gnm_prefix *local, uint32_t n_local,
+                                  const gnm_registry_opts *opts, hipStream_t stream,
+                                  gnm_registry **out) {
+  if (!out) return fail(GNM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (n_prefixes > 0 && !sites) return fail(GNM_E_INVAL, "sites is NULL");
+  if (n_local > 0 && !local) return fail(GNM_E_INVAL, "local is NULL");
+  if (n_sites == 0 || n_sites > kMaxSites) return fail(GNM_E_INVAL, "n_sites out of range");
+  gnm_registry_opts o{};
+  if (opts) o = *opts;
+  const uint32_t root_bits = o.root_bits ? o.root_bits : 12u;
+  const uint32_t list_max = o.list_max ? o.list_max : 16u;
+  const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsMax;
+  if (root_bits < 8 || root_bits > 15) return fail(GNM_E_INVAL, "root_bits must be 8..15");
+  if (list_max < 2 || list_max > kListCountMax) return fail(GNM_E_INVAL, "list_max must be 2..64");
+  if (lds_budget > kLdsMax || lds_budget < (4u << root_bits))
+    return fail(GNM_E_INVAL, "lds_bytes cannot hold the root table");
+
+  gnm_registry *r = new (std::nothrow) gnm_registry();
+  if (!r) return fail(GNM_E_NOMEM, "host allocation failed");
+  try {
+    r->n_sites = n_sites;
+    r->root_bits = root_bits;
+    r->list_max = list_max;
+    r->info.n_prefixes_in = n_prefixes;
+
+    // validate and normalise
+    std::vector<Pfx> p;
+    p.reserve(n_prefixes);
+    for (uint64_t i = 0; i < n_prefixes; ++i) {
+      const gnm_prefix &s = sites[i];
+      if (s.len > 32) { delete r; return fail(GNM_E_INVAL, "prefix length > 32"); }
+      if (s.site >= n_sites) { delete r; return fail(GNM_E_INVAL, "site id >= n_sites"); }
+      const uint32_t a = s.addr & mask_of(s.len);
+      if (a != s.addr) r->info.n_host_bits++;
+      p.push_back({a, s.len, s.site});
+    }
+    std::sort(p.begin(), p.end(), pfx_less);
+    std::vector<Pfx> d;
+    d.reserve(p.size());
+    for (const Pfx &q : p) {
+      if (!d.empty() && d.back().addr == q.addr && d.back().len == q.len) {
+        if (d.back().site != q.site) { delete r; return fail(GNM_E_CONFLICT, "prefix registered to two sites"); }
+        r->info.n_duplicates++;
+        continue;
+      }
+      d.push_back(q);
+    }
+    r->info.n_prefixes = d.size();
+
+    // local set -> disjoint inclusive ranges
+    std::vector<std::pair<uint32_t, uint32_t>> lr;
+    for (uint32_t j = 0; j < n_local; ++j) {
+      if (local[j].len > 32) { delete r; return fail(GNM_E_INVAL, "local prefix length > 32"); }
+      const uint32_t m = mask_of(local[j].len);
+      lr.push_back({local[j].addr & m, (local[j].addr & m) | ~m});
+    }
+    std::sort(lr.begin(), lr.end());
+    for (const auto &x : lr) {
+      if (!r->local_lo.empty() && (uint64_t)x.first <= (uint64_t)r->local_hi.back() + 1ull) {
+        r->local_hi.back() = std::max(r->local_hi.back(), x.second);
+      } else {
+        r->local_lo.push_back(x.first);
+        r->local_hi.push_back(x.second);
+      }
+    }
+    if (r->local_lo.size() > kMaxLocalRanges) {
+      delete r;
+      return fail(GNM_E_UNSUPPORTED, "local set needs more than 32 disjoint ranges");
+    }
+
+    // longest-prefix-match intervals and the trie layout
+    const std::vector<Interval> iv = resolve(d, n_sites);
+    r->info.n_intervals = iv.size();
+    Layout lay{&iv, list_max, {}, {}, {}};
+    r->root.resize((size_t)1 << root_bits);
+    for (uint64_t b = 0; b < ((uint64_t)1 << root_bits); ++b) {
+      const uint32_t e = lay.cell(b << (32 - root_bits), 32 - root_bits);
+      r->root[b] = e;
+    }
+    if (lay.overflow) { delete r; return fail(GNM_E_NOMEM, "lookup structure exceeds its index range"); }
+    r->nodes.swap(lay.nodes);
+    r->keys.swap(lay.keys);
+    r->vals.swap(lay.vals);
+    r->info.n_nodes = r->nodes.size() ? 0 : 0;
+    {
+      // count node blocks by walking NODE entries
+      uint64_t nn = 0;
+      for (uint32_t e : r->root) nn += (e >> kKindShift) == kKindNode;
+      for (uint32_t e : r->nodes) nn += (e >> kKindShift) == kKindNode;
+      r->info.n_nodes = nn;
+    }
+    r->info.n_list_entries = r->keys.size();
+    plan_lds(r, lds_budget);
+  } catch (const std::bad_alloc &) {
+    delete r;
+    return fail(GNM_E_NOMEM, "host allocation failed");
+  }
+
+  r->info.n_sites = n_sites;
+  r->info.n_local_ranges = (uint32_t)r->local_lo.size();
+  r->info.root_bits = r->root_bits;
+  r->info.list_max = r->list_max;
+  r->info.lists_in_lds = r->lists_in_lds;
+  r->info.acc_in_lds = r->acc_in_lds;
+  r->info.lds_bytes = r->lds_bytes;
+
+  if (o.flags & GNM_REG_HOST_ONLY) {
+    *out = r;
+    return GNM_OK;
+  }
+
+  // device upload: root | nodes | keys | vals, each 256-byte aligned
+  auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+  const uint64_t b_root = 4ull * r->root.size(), b_nodes = 4ull * r->nodes.size();
+  const uint64_t b_keys = 4ull * r->keys.size(), b_vals = 4ull * r->vals.size();
+  const uint64_t o_nodes = al(b_root), o_keys = o_nodes + al(b_nodes), o_vals = o_keys + al(b_keys);
+  const uint64_t total = o_vals + al(b_vals) + 256;
+  hipError_t e = hipGetDevice(&r->device);
+  if (e == hipSuccess) e = hipMalloc(&r->d_buf, total);
+  if (e != hipSuccess) {
+    set_last_error(std::string("registry upload: ") + hipGetErrorString(e));
+    delete r;
+    return e == hipErrorOutOfMemory ? GNM_E_NOMEM : GNM_E_HIP;
+  }
+  char *base = (char *)r->d_buf;
+  r->d_root = (const uint32_t *)base;
+  r->d_nodes = (const uint32_t *)(base + o_nodes);
+  r->d_keys = (const uint32_t *)(base + o_keys);
+  r->d_vals = (const uint32_t *)(base + o_vals);
+  r->d_bytes = total;
+  struct Part { const void *h; void *d; uint64_t b; } parts[] = {
+      {r->root.data(), (void *)r->d_root, b_root}, {r->nodes.data(), (void *)r->d_nodes, b_nodes},
+      {r->keys.data(), (void *)r->d_keys, b_keys}, {r->vals.data(), (void *)r->d_vals, b_vals}};
+  for (const Part &q : parts) {
+    if (q.b == 0) continue;
+    e = hipMemcpyAsync(q.d, q.h, q.b, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) break;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    set_last_error(std::string("registry upload: ") + hipGetErrorString(e));
+    (void)hipFree(r->d_buf);
+    delete r;
+    return GNM_E_HIP;
+  }
+  r->host_only = false;
+  r->info.device_bytes = total;
+  *out = r;
+  return GNM_OK;
+}
+
+extern "C" int gnm_registry_free(gnm_registry *reg) {
+  if (!reg) return GNM_OK;
+  int rc = GNM_OK;
+  if (reg->d_buf) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != reg->device) (void)hipSetDevice(reg->device);
+    hipError_t e = hipFree(reg->d_buf);
+    if (cur != reg->device && cur >= 0) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+      set_last_error(std::string("registry free: ") + hipGetErrorString(e));
+      rc = GNM_E_HIP;
+    }
+  }
+  delete reg;
+  return rc;
+}
+
+extern "C" int gnm_registry_info_get(const gnm_registry *reg, gnm_registry_info *info) {
+  if (!reg || !info) return fail(GNM_E_INVAL, "NULL argument");
+  *info = reg->info;
+  return GNM_OK;
+}
+
+extern "C" uint64_t gnm_acc_rows(const gnm_registry *reg) { return reg ? reg->rows() : 0; }
+
+extern "C" int gnm_registry_lookup_host(const gnm_registry *reg, const uint32_t *ip, uint64_t n,
+                                        uint32_t *site_out, uint8_t *local_out) {
+  if (!reg || (n > 0 && !ip)) return fail(GNM_E_INVAL, "NULL argument");
+  for (uint64_t i = 0; i < n; ++i) {
+    if (site_out) site_out[i] = host_lookup(reg, ip[i]);
+    if (local_out) local_out[i] = host_is_local(reg, ip[i]) ? 1 : 0;
+  }
+  return GNM_OK;
+}
+
+extern "C" const char *gnm_strerror(int code) {
+  switch (code) {
+    case GNM_OK: return "ok";
+    case GNM_E_INVAL: return "invalid argument";
+    case GNM_E_CONFLICT: return "prefix registered to two different sites";
+    case GNM_E_NOMEM: return "out of memory";
+    case GNM_E_HIP: return "HIP runtime error";
+    case GNM_E_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+extern "C" const char *gnm_last_error(void) { return gnm::g_last_error.c_str(); }
+
+extern "C" const char *gnm_version(void) { return "gnm 0.1.0 (gfx950)"; }

@@ -1,0 +1,41 @@
+// Registry object shared by the host builder (registry.cpp) and the device
+// entry points (kernels.hip).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gnm.h"
+#include "gnm_internal.h"
+
+struct gnm_registry {
+  uint32_t n_sites = 0;
+  uint32_t root_bits = 0;
+  uint32_t list_max = 0;
+
+  // host copy of the lookup structure (see gnm_internal.h)
+  std::vector<uint32_t> root, nodes, keys, vals;
+  // local set as disjoint inclusive ranges [lo, hi], sorted
+  std::vector<uint32_t> local_lo, local_hi;
+
+  gnm_registry_info info{};
+
+  // device copy (one allocation)
+  bool host_only = true;
+  int device = -1;
+  void *d_buf = nullptr;
+  const uint32_t *d_root = nullptr, *d_nodes = nullptr, *d_keys = nullptr, *d_vals = nullptr;
+  uint64_t d_bytes = 0;
+
+  // launch-time LDS plan
+  bool lists_in_lds = false;
+  bool acc_in_lds = false;
+  uint32_t lds_off_keys = 0, lds_off_vals = 0, lds_off_acc = 0, lds_bytes = 0;
+
+  uint64_t rows() const { return 2ull * (n_sites + 1ull) + 1ull; }
+};
+
+namespace gnm {
+void set_last_error(const std::string &s);
+}

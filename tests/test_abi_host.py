@@ -1,0 +1,142 @@
+"""C-ABI surface and host-side logic of libgnm (CPU only: no device calls).
+
+The library must load without a GPU, export every function include/gnm.h
+declares, and build registries host-only; the host walk of the built trie is
+checked against the oracle at every interval boundary (so the layout builder
+is pinned before any kernel runs).
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1108_1785_amd as gnm
+from oracle import brute
+from tests._helpers import boundary_points, ip, random_tiny_registry, worked_example
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "gnm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gnm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(gnm.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    L = gnm.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", gnm.LIB_PATH], capture_output=True, text=True).stdout
+    for name in _declared():
+        assert re.search(r"\bT %s\b" % name, out), name
+
+
+def test_strings_and_defaults():
+    assert gnm.version().startswith("gnm")
+    L = gnm.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.gnm_strerror(code)
+    p = L.gnm_params_default()
+    assert p.bulk_bytes == 1_000_000 and p.flags == 0 and p.records_per_thread == 0
+
+
+def _host_reg(sites, local, n_sites, **kw):
+    a = [s[0] for s in sites]
+    l = [s[1] for s in sites]
+    s = [s[2] for s in sites]
+    return gnm.Registry(a, l, s, n_sites, [x[0] for x in local], [x[1] for x in local], host_only=True, **kw)
+
+
+def test_worked_example_host_lookup():
+    sites, local, S, recs, exp, g = worked_example()
+    reg = _host_reg(sites, local, S)
+    assert reg.rows == 2 * S + 3
+    q = np.array([ip(a) for a, _ in g["lpm_spot_checks"]], dtype=np.uint32)
+    site, loc = reg.lookup_host(q)
+    assert site.tolist() == [s for _, s in g["lpm_spot_checks"]]
+    site, loc = reg.lookup_host(np.array([ip("198.18.5.1"), ip("198.19.0.0"), ip("198.17.255.255")], np.uint32))
+    assert loc.tolist() == [True, False, False]
+
+
+@pytest.mark.parametrize("root_bits,list_max", [(8, 2), (8, 64), (12, 16), (15, 2), (15, 64), (10, 3)])
+@pytest.mark.parametrize("seed", range(12))
+def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max):
+    rng = np.random.default_rng(1000 + seed)
+    n_sites, sites, local = random_tiny_registry(rng, n_prefixes=int(rng.integers(0, 60)))
+    reg = _host_reg(sites, local, n_sites, root_bits=root_bits, list_max=list_max)
+    orc = oracle.Registry([s[0] for s in sites], [s[1] for s in sites], [s[2] for s in sites], n_sites,
+                          [x[0] for x in local], [x[1] for x in local])
+    pts = np.array(boundary_points(sites + [(a, l, 0) for a, l in local]), dtype=np.uint32)
+    site, loc = reg.lookup_host(pts)
+    assert site.tolist() == orc.lookup(pts).tolist()
+    assert loc.tolist() == [brute.is_local(local, int(p)) for p in pts.tolist()]
+
+
+def test_host_trie_generated_registries():
+    import flowgen
+    for wl in (flowgen.PLAIN_SMALL, flowgen.PLAIN_LARGE):
+        r = flowgen.registry_for(wl)
+        reg = gnm.Registry.from_generated(r, host_only=True)
+        orc = oracle.Registry.from_generated(r)
+        pts = boundary_points(list(zip(r.addr.tolist(), r.length.tolist(), r.site.tolist())))
+        pts = np.array(pts, dtype=np.uint32)
+        assert (reg.lookup_host(pts)[0] == orc.lookup(pts)).all()
+        info = reg.info()
+        assert info["n_prefixes"] == r.n_prefixes and info["n_sites"] == r.n_sites
+        assert info["n_local_ranges"] == r.n_local
+
+
+def test_registry_info_counts_normalisation():
+    sites = [(ip("10.1.2.3"), 8, 1), (ip("10.0.0.0"), 8, 1), (ip("10.200.0.0"), 16, 0)]
+    reg = _host_reg(sites, [(ip("192.168.1.0"), 24), (ip("192.168.0.0"), 16)], 2)
+    info = reg.info()
+    assert info["n_prefixes_in"] == 3 and info["n_prefixes"] == 2
+    assert info["n_host_bits"] == 1 and info["n_duplicates"] == 1
+    assert info["n_local_ranges"] == 1  # nested local prefixes merge
+    assert info["n_intervals"] == 5     # none | 10/8 | 10.200/16 | 10/8 | none
+
+
+@pytest.mark.parametrize("sites,n_sites,local,code", [
+    ([(ip("10.0.0.0"), 8, 0), (ip("10.9.9.9"), 8, 1)], 2, [], gnm.GNM_E_CONFLICT),
+    ([(ip("10.0.0.0"), 33, 0)], 1, [], gnm.GNM_E_INVAL),
+    ([(ip("10.0.0.0"), 8, 2)], 2, [], gnm.GNM_E_INVAL),
+    ([], 0, [], gnm.GNM_E_INVAL),
+    ([], 1, [(ip("10.0.0.0"), 40)], gnm.GNM_E_INVAL),
+    ([], 1, [(i << 20, 12) for i in range(0, 66, 2)], gnm.GNM_E_UNSUPPORTED),
+])
+def test_registry_errors(sites, n_sites, local, code):
+    with pytest.raises(gnm.GnmError) as e:
+        _host_reg(sites, local, n_sites)
+    assert e.value.code == code
+
+
+def test_build_option_errors():
+    for kw in (dict(root_bits=7), dict(root_bits=16), dict(list_max=1), dict(list_max=65)):
+        with pytest.raises(gnm.GnmError) as e:
+            _host_reg([], [], 1, **kw)
+        assert e.value.code == gnm.GNM_E_INVAL
+
+
+def test_device_calls_reject_host_only_registry_and_nulls():
+    L = gnm.lib()
+    reg = _host_reg([(ip("10.0.0.0"), 8, 0)], [], 1)
+    rec = gnm.RecordsC()
+    p = L.gnm_params_default()
+    rc = L.gnm_classify_aggregate(reg.handle, ctypes.byref(rec), None, 1, ctypes.byref(p), ctypes.c_void_p(8), None)
+    assert rc == gnm.GNM_E_UNSUPPORTED
+    rc = L.gnm_flag_suboptimal(reg.handle, ctypes.c_void_p(8), 1, 10, 0, ctypes.c_void_p(8), None)
+    assert rc == gnm.GNM_E_UNSUPPORTED
+    assert L.gnm_classify_aggregate(None, ctypes.byref(rec), None, 1, None, ctypes.c_void_p(8), None) == gnm.GNM_E_INVAL
+    assert L.gnm_flag_suboptimal(None, None, 1, 1, 0, None, None) == gnm.GNM_E_INVAL
+    assert L.gnm_acc_rows(None) == 0
+    assert L.gnm_registry_free(None) == 0
+    reg.close()

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer work, so the bar is bit-exact equality of every field of every row
+(tolerance 0) on the same seeded inputs: the worked example, generated
+windows of each workload (full size for the 100 k and 10 M windows), the
+batched form window by window, launch-shape and registry-layout variants, and
+edge cases (empty and ragged runs, tile boundaries, maximum contention,
+wrap-around and saturation).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import flowgen
+import oracle
+import paper_1108_1785_amd as gnm
+from oracle import brute
+from tests._gpu import diff, flags, run, to_device
+from tests._helpers import M64, random_tiny_registry, soa, worked_example
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _regs(sites, local, n_sites, **kw):
+    a = [s[0] for s in sites]
+    l = [s[1] for s in sites]
+    s = [s[2] for s in sites]
+    la = [x[0] for x in local]
+    ll = [x[1] for x in local]
+    return gnm.Registry(a, l, s, n_sites, la, ll, **kw), oracle.Registry(a, l, s, n_sites, la, ll)
+
+
+def test_worked_example(torch_cuda):
+    say("case: worked example")
+    sites, local, S, recs, exp, g = worked_example()
+    reg, _ = _regs(sites, local, S)
+    got = run(reg, soa(recs), bulk_bytes=g["bulk_bytes"])
+    assert got.tolist() == exp
+    assert flags(reg, got, g["threshold_bps"]).tolist() == g["expected_flags"]
+
+
+_SMALL = {}
+
+
+def _small():
+    if not _SMALL:
+        r = flowgen.registry_for(flowgen.PLAIN_SMALL)
+        _SMALL["reg"] = r
+        _SMALL["orc"] = oracle.Registry.from_generated(r)
+        _SMALL["rec"] = flowgen.records_for(flowgen.PLAIN_SMALL, reg=r)
+    return _SMALL
+
+
+@pytest.mark.parametrize("rpt", [0, 1, 2, 4, 8])
+def test_plain_small_full(torch_cuda, rpt):
+    say("case: plain-small 100k records, records_per_thread", rpt)
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    exp = s["orc"].classify_aggregate(s["rec"])
+    got = run(reg, s["rec"], records_per_thread=rpt)
+    assert (got == exp).all(), diff(got, exp)
+    assert (flags(reg, got) == oracle.flags(exp, s["reg"].n_sites)).all()
+
+
+@pytest.mark.parametrize("grid", [1, 3, 64, 256, 1000])
+def test_plain_small_grid_shapes(torch_cuda, grid):
+    say("case: plain-small grid_blocks", grid)
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    exp = s["orc"].classify_aggregate(s["rec"])
+    got = run(reg, s["rec"], grid_blocks=grid)
+    assert (got == exp).all(), diff(got, exp)
+
+
+@pytest.mark.parametrize("kw", [dict(root_bits=8, list_max=2), dict(root_bits=15, list_max=64),
+                                dict(root_bits=10, list_max=3), dict(lds_bytes=4096 + 256, root_bits=10),
+                                dict(lds_bytes=1024, root_bits=8)])
+def test_registry_layout_variants(torch_cuda, kw):
+    say("case: layout", kw)
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"], **kw)
+    info = reg.info()
+    say("  info", info)
+    exp = s["orc"].classify_aggregate(s["rec"])
+    got = run(reg, s["rec"])
+    assert (got == exp).all(), diff(got, exp)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 1023, 1024, 1025, 4095, 4096, 4097, 8191, 8193, 70001])
+def test_ragged_sizes(torch_cuda, n):
+    say("case: ragged n", n)
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"].slice(0, n)
+    exp = s["orc"].classify_aggregate(rec)
+    got = run(reg, rec)
+    assert (got == exp).all(), diff(got, exp)
+
+
+def test_edge_registries_and_records(torch_cuda):
+    from tests.test_oracle_pins import _edge_records
+    for seed in range(30):
+        say("case: edge registry seed", seed)
+        rng = np.random.default_rng(500 + seed)
+        n_sites, sites, local = random_tiny_registry(rng, n_prefixes=int(rng.integers(0, 60)),
+                                                     n_local=int(rng.integers(0, 4)))
+        recs = _edge_records(rng, int(rng.integers(0, 3000)), sites, local)
+        bulk = int(rng.choice([0, 1_000_000, 1 << 40]))
+        kw = dict(root_bits=int(rng.integers(8, 16)), list_max=int(rng.integers(2, 65)))
+        reg, orc = _regs(sites, local, n_sites, **kw)
+        rec = soa(recs)
+        exp = orc.classify_aggregate(rec, bulk)
+        got = run(reg, rec, bulk_bytes=bulk, records_per_thread=int(rng.choice([1, 2, 4, 8])))
+        assert (got == exp).all(), (seed, diff(got, exp))
+        if seed < 5:
+            assert got.tolist() == brute.classify_aggregate(sites, local, n_sites, recs, bulk)
+
+
+def test_max_contention_one_row(torch_cuda):
+    say("case: all records in one row")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"].slice(0, 50_000).copy()
+    rec.src_ip[:] = rec.src_ip[0]
+    rec.dst_ip[:] = rec.dst_ip[0]
+    exp = s["orc"].classify_aggregate(rec)
+    assert int((exp[:, 0] > 0).sum()) == 1
+    got = run(reg, rec)
+    assert (got == exp).all(), diff(got, exp)
+
+
+def test_all_nodir_and_all_unmatched(torch_cuda):
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"].slice(0, 30_000)
+    a = rec.copy()
+    a.src_ip[:] = 0xF0000001  # neither endpoint local: NODIR
+    a.dst_ip[:] = 0xF0000002
+    b = rec.copy()
+    b.src_ip[:] = s["reg"].local_addr[0] | 5
+    b.dst_ip[:] = 0xF0000000 | (np.arange(b.n, dtype=np.uint32) & 0xFFFF)  # remote in no site
+    for name, r in (("nodir", a), ("unmatched", b)):
+        say("case:", name)
+        exp = s["orc"].classify_aggregate(r)
+        got = run(reg, r)
+        assert (got == exp).all(), diff(got, exp)
+
+
+def test_wrap_and_saturation(torch_cuda):
+    say("case: 2^63-byte records (sums wrap, rates saturate)")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    r = s["rec"].slice(0, 20_000).copy()
+    r.bytes[::3] = np.uint64(1 << 63) + np.uint64(12345)
+    r.bytes[1::7] = np.uint64(M64)
+    r.packets[::5] = np.uint32(0xFFFFFFFF)
+    exp = s["orc"].classify_aggregate(r)
+    assert int(exp[:, 7].max()) == M64
+    got = run(reg, r)
+    assert (got == exp).all(), diff(got, exp)
+
+
+def test_near_integer_rates(torch_cuda):
+    say("case: near-integer quotients")
+    rng = np.random.default_rng(3)
+    cases = []
+    while len(cases) < 20000:
+        d = int(rng.integers(2, 1 << 32))
+        if d % 2 == 0 or d % 5 == 0:
+            continue
+        b = (-pow(8000, -1, d)) % d
+        b += d * int(rng.integers(0, max(1, ((1 << 40) - b) // d)))
+        if b > 1_000_000:
+            cases.append((b, d))
+    sites = [(0, 0, 0)]
+    local = [(0x0A000000, 8)]
+    recs = [(0x0A000001, 0x0B000000 + i, b, 1, 7, (7 + d) & 0xFFFFFFFF) for i, (b, d) in enumerate(cases)]
+    reg, orc = _regs(sites, local, 1)
+    rec = soa(recs)
+    exp = orc.classify_aggregate(rec)
+    got = run(reg, rec)
+    assert (got == exp).all(), diff(got, exp)
+    # one record per run pins each rate individually (min = max = rate)
+    for b, d in cases[:200]:
+        one = soa([(0x0A000001, 0x0B000000, b, 1, 0, d)])
+        g1 = run(reg, one)
+        assert int(g1[1, 6]) == (8000 * b) // d == int(g1[1, 7])
+
+
+def test_accumulate_flag(torch_cuda):
+    import torch
+    say("case: GNM_ACCUMULATE over two halves")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"]
+    exp = s["orc"].classify_aggregate(rec)
+    acc = torch.empty((1, reg.rows, 8), dtype=torch.int64, device="cuda:0")
+    run(reg, rec.slice(0, 40_000), acc=acc)
+    got = run(reg, rec.slice(40_000, rec.n), acc=acc, accumulate=True)
+    assert (got == exp).all(), diff(got, exp)
+
+
+def test_deterministic_repeats(torch_cuda):
+    say("case: repeat runs identical")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    d = to_device(s["rec"])
+    a = run(reg, s["rec"], dev_rec=d)
+    for _ in range(3):
+        assert (run(reg, s["rec"], dev_rec=d) == a).all()
+    perm = flowgen.permuted(s["rec"], np.random.default_rng(9))
+    assert (run(reg, perm) == a).all()
+
+
+def test_batched_windows(torch_cuda):
+    say("case: batched 256 windows (scaled to 6M records)")
+    r = flowgen.registry_for(flowgen.PLAIN_SMALL)
+    rec = flowgen.records_for(flowgen.BATCHED, reg=r, n=6_000_000)
+    off = rec.window_offsets.copy()
+    assert len(off) == 257
+    orc = oracle.Registry.from_generated(r)
+    exp = orc.classify_aggregate(rec)
+    reg = gnm.Registry.from_generated(r)
+    for rpt, grid in ((0, 0), (8, 0), (1, 37), (4, 2000)):
+        say("  rpt", rpt, "grid", grid)
+        got = run(reg, rec, records_per_thread=rpt, grid_blocks=grid)
+        assert (got == exp).all(), diff(got, exp)
+    fexp = oracle.flags(exp, r.n_sites)
+    assert (flags(reg, got) == fexp).all()
+
+
+def test_batched_with_empty_windows(torch_cuda):
+    say("case: batched with empty and tiny windows")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"]
+    cuts = [0, 0, 0, 1, 1, 64, 65, 5000, 5000, 70000, 99999, rec.n, rec.n]
+    off = np.array(cuts, dtype=np.uint64)
+    exp = s["orc"].classify_aggregate(rec, window_offsets=off)
+    for grid in (0, 1, 7, 300):
+        got = run(reg, rec, window_offsets=off, grid_blocks=grid)
+        assert (got == exp).all(), diff(got, exp)
+    assert (got[0, :, 6] == np.uint64(M64)).all() and (got[0, :, 0] == 0).all()
+
+
+def test_plain_large_full_size(torch_cuda):
+    say("case: plain-large 10M records (full size, bench launch shape)")
+    r = flowgen.registry_for(flowgen.PLAIN_LARGE)
+    rec = flowgen.records_for(flowgen.PLAIN_LARGE, reg=r)
+    orc = oracle.Registry.from_generated(r)
+    exp = orc.classify_aggregate(rec)
+    reg = gnm.Registry.from_generated(r)
+    say("  info", reg.info())
+    got = run(reg, rec)
+    assert (got == exp).all(), diff(got, exp)
+    assert (flags(reg, got) == oracle.flags(exp, r.n_sites)).all()
