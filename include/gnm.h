@@ -112,18 +112,22 @@ typedef struct {
 typedef struct {
   uint64_t bulk_bytes;         /* bulk iff bytes > bulk_bytes and dur > 0 */
   uint32_t flags;              /* GNM_ACCUMULATE */
-  uint32_t records_per_thread; /* 0 = automatic; else 1, 2, 4 or 8 */
+  uint32_t records_per_thread; /* 0 = automatic (4); else 1, 2 or 4 */
   uint32_t grid_blocks;        /* 0 = automatic; else workgroups of the launch */
   uint32_t reserved;
+  void *workspace;             /* optional DEVICE scratch, 16-byte aligned; see below */
+  uint64_t workspace_bytes;    /* its size; >= gnm_workspace_bytes(reg, grid_blocks) to be used */
 } gnm_params;
 
-#define GNM_REG_HOST_ONLY 0x1u /* gnm_registry_opts.flags: build host structure only */
+#define GNM_REG_HOST_ONLY 0x1u   /* gnm_registry_opts.flags: build host structure only */
+#define GNM_REG_FORCE_WIDE 0x2u  /* every multi-interval root cell gets a wide node */
+#define GNM_REG_FORCE_LINES 0x4u /* root cells of <= list_max intervals stay leaf lines */
 
 /* Registry build options (NULL = defaults). */
 typedef struct {
   uint32_t flags;          /* GNM_REG_HOST_ONLY: no device upload (inspection only) */
   uint32_t root_bits;      /* 0 = automatic; else 8..15 bits indexed by the LDS-resident top level */
-  uint32_t list_max;       /* 0 = automatic; else 2..64 intervals searched per leaf */
+  uint32_t list_max;       /* 0 = automatic (8); else 2..8 intervals per 64-byte leaf line */
   uint32_t lds_bytes;      /* 0 = automatic; LDS budget of the lookup structure */
 } gnm_registry_opts;
 
@@ -134,14 +138,14 @@ typedef struct {
   uint64_t n_host_bits;     /* prefixes that had host bits set (cleared) */
   uint64_t n_duplicates;    /* exact duplicates for the same site (dropped) */
   uint64_t n_intervals;     /* maximal address intervals with one answer */
-  uint64_t n_nodes;         /* inner direct-index nodes below the root */
-  uint64_t n_list_entries;  /* interval starts held in leaf lists */
+  uint64_t n_nodes;         /* wide inner nodes below the root */
+  uint64_t n_leaf_lines;    /* 64-byte leaf lines (up to 8 intervals each) */
   uint64_t device_bytes;    /* device memory held by the registry */
   uint32_t n_sites;
   uint32_t n_local_ranges;  /* disjoint address ranges of the local set */
   uint32_t root_bits;
   uint32_t list_max;
-  uint32_t lists_in_lds;    /* 1 if leaf lists are staged into LDS */
+  uint32_t lines_in_lds;    /* 1 if leaf lines are staged into LDS */
   uint32_t acc_in_lds;      /* 1 if the whole per-block accumulator table fits LDS */
   uint32_t lds_bytes;       /* LDS a classify workgroup uses */
   uint32_t reserved;
@@ -188,8 +192,20 @@ uint64_t gnm_acc_rows(const gnm_registry *reg);
 int gnm_registry_lookup_host(const gnm_registry *reg, const uint32_t *ip, uint64_t n,
                              uint32_t *site_out, uint8_t *local_out);
 
-/* Defaults: bulk_bytes 1,000,000, no flags, automatic launch shape. */
+/* Defaults: bulk_bytes 1,000,000, no flags, automatic launch shape, no workspace. */
 gnm_params gnm_params_default(void);
+
+/*
+ * gnm_workspace_bytes — size of the optional classify workspace for a launch
+ * of grid_blocks workgroups (0 = the automatic maximum on the registry's
+ * device).  With a workspace, each workgroup writes its final LDS table there
+ * with plain stores and one small reduce kernel combines the tables; without
+ * one, the tables are merged with device-scope 64-bit atomics, which give the
+ * same result more slowly.  The workspace is caller-owned scratch: its
+ * contents before and after a call do not matter, and two calls in flight at
+ * the same time must not share one.  0 for a NULL registry.
+ */
+uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks);
 
 /*
  * gnm_classify_aggregate — §III.B.2 (TransRate Kernel) with the definition
@@ -209,12 +225,14 @@ gnm_params gnm_params_default(void);
  *                   window-major.  Initialised by the call unless
  *                   p->flags has GNM_ACCUMULATE (then added into).
  *   stream          the caller's stream.
- * Enqueues an initialisation kernel (unless accumulating) and one classify
- * kernel; with several windows the launch is persistent and each workgroup
- * walks a balanced contiguous slice of all records, flushing its LDS table at
- * window changes.  Errors: GNM_E_INVAL (null pointers, n_windows = 0,
- * offsets NULL with n_windows > 1, records_per_thread not 0/1/2/4/8),
- * GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
+ * Enqueues up to three kernels: table initialisation (skipped when
+ * accumulating, or when a single window is rebuilt entirely by the reduce
+ * step), the classify kernel, and (with a usable p->workspace) the reduce
+ * kernel.  Each classify workgroup walks a balanced contiguous slice of all
+ * records, flushing its LDS table at window changes.  Errors: GNM_E_INVAL
+ * (null pointers, n_windows = 0, offsets NULL with n_windows > 1,
+ * records_per_thread not 0/1/2/4), GNM_E_UNSUPPORTED (host-only registry),
+ * GNM_E_HIP (launch failed).
  */
 int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
                            const uint64_t *window_offsets, uint32_t n_windows,

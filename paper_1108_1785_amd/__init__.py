@@ -26,6 +26,8 @@ GNM_E_HIP = -4
 GNM_E_UNSUPPORTED = -5
 GNM_ACCUMULATE = 0x1
 GNM_REG_HOST_ONLY = 0x1
+GNM_REG_FORCE_WIDE = 0x2
+GNM_REG_FORCE_LINES = 0x4
 
 ACC_FIELDS = ("flows", "bytes", "packets", "duration_ms", "bulk_flows",
               "rate_sum_bps", "rate_min_bps", "rate_max_bps")
@@ -33,7 +35,7 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
-           "gnm_registry_lookup_host", "gnm_params_default", "gnm_classify_aggregate",
+           "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_classify_aggregate",
            "gnm_flag_suboptimal", "gnm_strerror", "gnm_last_error", "gnm_version")
 
 
@@ -51,7 +53,8 @@ class RecordsC(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("bulk_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("records_per_thread", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_uint64)]
 
 
 class RegistryOpts(ctypes.Structure):
@@ -61,9 +64,9 @@ class RegistryOpts(ctypes.Structure):
 
 class RegistryInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("n_prefixes_in", "n_prefixes", "n_host_bits", "n_duplicates",
-                                               "n_intervals", "n_nodes", "n_list_entries", "device_bytes")] + \
+                                               "n_intervals", "n_nodes", "n_leaf_lines", "device_bytes")] + \
                [(n, ctypes.c_uint32) for n in ("n_sites", "n_local_ranges", "root_bits", "list_max",
-                                               "lists_in_lds", "acc_in_lds", "lds_bytes", "reserved")]
+                                               "lines_in_lds", "acc_in_lds", "lds_bytes", "reserved")]
 
     def as_dict(self) -> Dict[str, int]:
         return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
@@ -107,6 +110,8 @@ def lib():
         L.gnm_registry_lookup_host.restype = ctypes.c_int
         L.gnm_params_default.argtypes = []
         L.gnm_params_default.restype = Params
+        L.gnm_workspace_bytes.argtypes = [P, ctypes.c_uint32]
+        L.gnm_workspace_bytes.restype = ctypes.c_uint64
         L.gnm_classify_aggregate.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32,
                                              ctypes.POINTER(Params), P, P]
         L.gnm_classify_aggregate.restype = ctypes.c_int
@@ -151,11 +156,14 @@ class Registry:
 
     def __init__(self, addr, length, site, n_sites: int, local_addr=(), local_len=(),
                  root_bits: int = 0, list_max: int = 0, lds_bytes: int = 0,
-                 host_only: bool = False, stream=None):
+                 host_only: bool = False, stream=None, layout: str = "auto"):
+        """layout: "auto", "wide" (GNM_REG_FORCE_WIDE) or "lines" (GNM_REG_FORCE_LINES)."""
         L = lib()
         sites, n = _prefix_array(addr, length, site)
         local, nl = _prefix_array(local_addr, local_len)
-        opts = RegistryOpts(GNM_REG_HOST_ONLY if host_only else 0, root_bits, list_max, lds_bytes)
+        flags = (GNM_REG_HOST_ONLY if host_only else 0) | \
+            {"auto": 0, "wide": GNM_REG_FORCE_WIDE, "lines": GNM_REG_FORCE_LINES}[layout]
+        opts = RegistryOpts(flags, root_bits, list_max, lds_bytes)
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(0) if host_only else _stream_handle(stream)
         _check(L.gnm_registry_build(sites, n, int(n_sites), local, nl, ctypes.byref(opts), st,
@@ -225,20 +233,40 @@ def records_struct(rec: Dict[str, "object"], n: Optional[int] = None) -> Records
 
 
 def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_per_thread: int = 0,
-                grid_blocks: int = 0) -> Params:
+                grid_blocks: int = 0, workspace=None) -> Params:
     p = lib().gnm_params_default()
     p.bulk_bytes = int(bulk_bytes)
     p.flags = GNM_ACCUMULATE if accumulate else 0
     p.records_per_thread = int(records_per_thread)
     p.grid_blocks = int(grid_blocks)
+    if workspace is not None:
+        if not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous device tensor")
+        p.workspace = workspace.data_ptr()
+        p.workspace_bytes = workspace.numel() * workspace.element_size()
     return p
+
+
+def workspace_bytes(reg: Registry, grid_blocks: int = 0) -> int:
+    """gnm_workspace_bytes: scratch size for a launch of grid_blocks workgroups (0 = automatic)."""
+    return int(lib().gnm_workspace_bytes(reg.handle, int(grid_blocks)))
+
+
+def make_workspace(reg: Registry, grid_blocks: int = 0, device=None):
+    """A device byte tensor of gnm_workspace_bytes(reg, grid_blocks) bytes."""
+    import torch
+    return torch.empty(workspace_bytes(reg, grid_blocks), dtype=torch.uint8,
+                       device=device if device is not None else "cuda")
 
 
 def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1,
                        bulk_bytes: int = 1_000_000, accumulate: bool = False,
                        records_per_thread: int = 0, grid_blocks: int = 0, stream=None,
-                       n: Optional[int] = None) -> None:
-    """gnm_classify_aggregate: acc is a device tensor of n_windows*rows*8 64-bit words."""
+                       n: Optional[int] = None, workspace=None) -> None:
+    """gnm_classify_aggregate: acc is a device tensor of n_windows*rows*8 64-bit words.
+
+    workspace: optional device tensor from make_workspace() (faster table merge).
+    """
     c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
     if acc.element_size() * acc.numel() < n_windows * reg.rows * 64 or not acc.is_cuda:
         raise ValueError("acc must be a device tensor of n_windows * rows * 64 bytes")
@@ -247,7 +275,7 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
         if window_offsets.element_size() != 8 or window_offsets.numel() < n_windows + 1 or not window_offsets.is_cuda:
             raise ValueError("window_offsets must be a device tensor of n_windows+1 64-bit offsets")
         off = window_offsets.data_ptr()
-    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks)
+    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace)
     _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
                                         ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
                                         _stream_handle(stream)), "gnm_classify_aggregate")

@@ -6,21 +6,37 @@
 //
 // The registry's answer is a step function over the 32-bit address space: it
 // is constant on maximal intervals between prefix starts and ends.  It is laid
-// out as a direct-indexed trie whose entries are 32-bit words:
+// out as a direct-indexed trie:
 //
-//   root[2^root_bits]   indexed by the top root_bits of the address (staged
-//                       into LDS by every classify workgroup);
-//   nodes[]             inner nodes, each indexed by the next up-to-8 bits;
-//   keys[] / vals[]     leaf lists: the sorted interval starts falling in one
-//                       trie cell (first entry = the cell's base address) and
-//                       the site code of each interval.
+//   root[2^root_bits]   32-bit entries indexed by the top root_bits of the
+//                       address (staged into LDS by every classify workgroup);
+//   wide[]              inner nodes: arrays of 16-byte entries indexed by the
+//                       next up-to-8 address bits;
+//   lines[]             leaf lines of 64 bytes for cells holding 2..8
+//                       intervals: 8 sorted interval starts (the first is the
+//                       cell's base address) then their 8 site codes; unused
+//                       slots repeat the last interval, so the answer is
+//                       sites[number of starts 1..7 that are <= address].
 //
-// Entry encoding (bits 31..30 = kind):
-//   LEAF  (2): bits 29..0 = site code (site id, or n_sites = no site);
-//   LIST  (0): bits 23..0 = offset into keys/vals, bits 29..24 = count - 1;
-//   NODE  (1): bits 29..0 = offset of the child node's first entry in nodes[].
+// Root entry (bits 31..30 = kind, bits 29..0 = payload):
+//   LEAF (2): site code (site id, or n_sites = no site);
+//   LINE (0): index of the cell's leaf line;
+//   NODE (1): index (in 16-byte entries) of the cell's wide node.
+// Wide-node entry, four 32-bit words x, y, z, w; kind = y >> 30:
+//   LEAF (2): z = site code;
+//   LINE (0): z = leaf line index;
+//   NODE (1): z = index of the next wide node;
+//   QUAD (3): up to 4 intervals of a cell of at most 2^16 addresses:
+//             starts as offsets from the cell base k1 = x & 0xFFFF,
+//             k2 = x >> 16, k3 = y & 0xFFFF (k0 = 0 implicit), sites as
+//             16-bit codes s0 = z & 0xFFFF, s1 = z >> 16, s2 = w & 0xFFFF,
+//             s3 = w >> 16; unused slots repeat the last interval.
 // A node below a cell that leaves `shift` address bits unresolved indexes
 // min(8, shift) bits; its children then leave shift - that many.
+//
+// Local set: besides the disjoint ranges, a map of 2 bits per /16 block of
+// the address space (4096 words of 16 blocks each): 0 = no local address,
+// 1 = every address local, 2 = partly local (decided by the ranges).
 #pragma once
 
 #include <cstdint>
@@ -28,16 +44,18 @@
 namespace gnm {
 
 constexpr uint32_t kKindShift = 30;
-constexpr uint32_t kKindList = 0u;
+constexpr uint32_t kKindLine = 0u;
 constexpr uint32_t kKindNode = 1u;
 constexpr uint32_t kKindLeaf = 2u;
+constexpr uint32_t kKindQuad = 3u;  // wide-node entries only
 constexpr uint32_t kPayloadMask = (1u << 30) - 1u;
-constexpr uint32_t kListOffsetBits = 24;
-constexpr uint32_t kListOffsetMask = (1u << kListOffsetBits) - 1u;
-constexpr uint32_t kListCountMax = 64;  // count - 1 fits 6 bits
+constexpr uint32_t kLineKeys = 8;     // interval starts per leaf line
+constexpr uint32_t kLineWords = 16;   // 8 starts + 8 site codes = 64 bytes
 constexpr uint32_t kNodeStrideMax = 8;
 
 constexpr uint32_t kMaxLocalRanges = 32;
+constexpr uint32_t kLocalMapWords = 4096;  // 65536 /16 blocks x 2 bits
+constexpr uint32_t kLocalNone = 0, kLocalFull = 1, kLocalPart = 2;
 constexpr uint32_t kMaxSites = 1u << 28;
 constexpr uint32_t kLdsMax = 160u * 1024u;
 
@@ -49,9 +67,7 @@ enum AccField : uint32_t { kCnt = 0, kBytes, kPackets, kDur, kRateSum, kRateMin,
 constexpr uint64_t kMaxRecordsPerFlush = 1ull << 31;
 
 inline uint32_t make_leaf(uint32_t site) { return (kKindLeaf << kKindShift) | site; }
-inline uint32_t make_list(uint32_t off, uint32_t count) {
-  return (kKindList << kKindShift) | ((count - 1u) << kListOffsetBits) | off;
-}
+inline uint32_t make_line(uint32_t index) { return (kKindLine << kKindShift) | index; }
 inline uint32_t make_node(uint32_t off) { return (kKindNode << kKindShift) | off; }
 
 }  // namespace gnm

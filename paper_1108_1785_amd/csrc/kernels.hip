@@ -8,17 +8,23 @@
 // non-caching loads (§III.B.2, GPU Kernel Optimization).  On CDNA4 the same
 // method is laid out as:
 //   * workgroups of 1024 lanes (16 wave64s) that each own a balanced,
-//     contiguous slice of the records and stream it with coalesced
-//     non-temporal SoA loads, R records per lane in flight;
-//   * the top level of the prefix trie (and, when small, the whole trie)
-//     staged once per workgroup into LDS;
+//     contiguous slice of the records, streamed with non-temporal 16-byte
+//     loads (4 consecutive records per lane per field), the next tile's loads
+//     in flight while the current tile is classified;
+//   * LDS-resident locality map (2 bits per /16) and trie root, and the trie's
+//     64-byte leaf lines as well when they fit; otherwise wide inner nodes
+//     whose 16-byte entries usually hold a whole cell, so one cached read
+//     resolves a lookup; the R lookups of a lane advance in lockstep so their
+//     memory accesses overlap;
 //   * a per-workgroup accumulator table in LDS (structure of arrays of u64,
-//     updated with ds_add/ds_min/ds_max_u64) flushed to the caller's HBM
-//     table with 64-bit global atomics once per (workgroup, window);
-//   * an exact integer rate: a correctly rounded f64 quotient, which is exact
-//     to within one unit for 8000*bytes < 2^53, corrected by one integer
-//     multiply-compare; a 64-bit integer long division covers larger byte
-//     counts.
+//     ds_add/ds_min/ds_max_u64);
+//   * an exact integer rate: a correctly rounded f64 quotient, within one of
+//     the answer for 8000*bytes < 2^53, corrected by one integer
+//     multiply-compare; a 64-bit long division covers larger byte counts;
+//   * each workgroup's final table written with plain coalesced stores to a
+//     caller workspace and combined by a small reduce kernel (device-scope
+//     atomics, which serialise across the chip, are used only for tables
+//     flushed mid-launch at window changes, or when no workspace is given).
 // Several windows go through one persistent launch: workgroups cut the
 // concatenated records into equal slices and flush at window boundaries.
 #include <hip/hip_runtime.h>
@@ -32,8 +38,15 @@
 namespace gnm {
 
 typedef unsigned long long u64;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+// Pointers into the global address space (not flat).
+typedef __attribute__((address_space(1))) const uint32_t gu32;
+typedef __attribute__((address_space(1))) const uint64_t gu64;
 
 constexpr uint32_t kThreads = 1024;
+constexpr uint32_t kRedRows = 16;  // reduce kernel: rows per workgroup
+constexpr uint32_t kRedSubs = 16;  // reduce kernel: partial tables summed in parallel per row
 
 struct LocalRanges {
   uint32_t n;
@@ -46,53 +59,118 @@ struct ClassifyArgs {
   const uint64_t *bytes;
   const uint32_t *packets, *first, *last;
   uint64_t n;
-  const uint64_t *woff;  // NULL: one window [0, n)
+  gu64 *woff;  // NULL: one window [0, n)
   uint32_t n_windows;
   uint32_t rows;
   uint64_t bulk_bytes;
   u64 *acc;  // n_windows * rows * 8 words
-  const uint32_t *root, *nodes, *keys, *vals;
+  gu32 *root, *wide, *lines, *lmap;
   uint32_t root_bits;
-  uint32_t n_list;
-  uint32_t lds_off_acc, lds_off_keys, lds_off_vals;
+  uint32_t n_line_words;
+  uint32_t lds_off_lmap, lds_off_acc, lds_off_lines;
+  u64 *ws;             // NULL: every table is flushed with atomics
+  uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
   LocalRanges local;
 };
 
 // ---------------------------------------------------------------- device helpers
 
-// Membership of ip in the local set (disjoint ranges in kernel arguments, so
-// the loop bound and operands are wave-uniform scalars).
-__device__ __forceinline__ bool is_local(const LocalRanges &L, uint32_t ip) {
+__device__ __forceinline__ bool in_ranges(const LocalRanges &L, uint32_t ip) {
   bool r = false;
   for (uint32_t j = 0; j < L.n; ++j) r |= (ip - L.lo[j]) <= L.span[j];
   return r;
 }
 
-// Longest-prefix match: site code of the interval containing ip.
-template <bool LISTS_LDS>
-__device__ __forceinline__ uint32_t lookup_site(uint32_t ip, const uint32_t *s_root,
-                                                const uint32_t *__restrict__ nodes,
-                                                const uint32_t *keys, const uint32_t *vals,
-                                                uint32_t root_bits) {
-  uint32_t shift = 32u - root_bits;
-  uint32_t e = s_root[ip >> shift];
-  // at most ceil(24 / 8) = 3 node levels lie below a root of >= 8 bits
-  for (int depth = 0; depth < 3 && (e >> kKindShift) == kKindNode; ++depth) {
-    const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
-    const uint32_t idx = (ip >> ns) & ((1u << (shift - ns)) - 1u);
-    e = nodes[(e & kPayloadMask) + idx];
-    shift = ns;
+// Locality from the LDS /16 map; the ranges decide only partly-local blocks.
+__device__ __forceinline__ bool is_local(const uint32_t *s_lmap, const LocalRanges &L, uint32_t ip) {
+  const uint32_t code = (s_lmap[ip >> 20] >> ((ip >> 15) & 30u)) & 3u;
+  if (code == kLocalPart) return in_ranges(L, ip);
+  return code == kLocalFull;
+}
+
+__device__ __forceinline__ uint32_t quad_site(u32x4 q, uint32_t off) {
+  const uint32_t pos = ((q.x & 0xFFFFu) <= off) + ((q.x >> 16) <= off) + ((q.y & 0xFFFFu) <= off);
+  const uint32_t lo = pos & 2u ? q.w : q.z;
+  return pos & 1u ? lo >> 16 : lo & 0xFFFFu;
+}
+
+// Longest-prefix match of R addresses at once: site codes of the intervals
+// containing ip[k] for lanes with act[k].  The R walks advance in lockstep
+// so that their memory accesses are in flight together.  A wide-node entry
+// costs one 16-byte read and usually resolves the address; a leaf line costs
+// one 64-byte line fetch (keys) and one read of the same line (site).
+template <int R, bool LINES_LDS>
+__device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const bool (&act)[R],
+                                             uint32_t (&site)[R], const uint32_t *s_root,
+                                             gu32 *wide, const uint32_t *s_lines, gu32 *g_lines,
+                                             uint32_t root_bits) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  uint32_t node[R], line[R], shift[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    shift[k] = 32u - root_bits;
+    const uint32_t e = act[k] ? s_root[ip[k] >> shift[k]] : (kKindLeaf << kKindShift);
+    const uint32_t kind = e >> kKindShift, pay = e & kPayloadMask;
+    site[k] = pay;
+    node[k] = kind == kKindNode ? pay : kNone;
+    line[k] = kind == kKindLine ? pay : kNone;
   }
-  if ((e >> kKindShift) == kKindLeaf) return e & kPayloadMask;
-  const uint32_t off = e & kListOffsetMask;
-  uint32_t len = ((e >> kListOffsetBits) & 63u) + 1u;
-  uint32_t lo = 0;
-  while (len > 1) {  // keys[off] is the cell base <= ip
-    const uint32_t half = len >> 1;
-    if (keys[off + lo + half] <= ip) lo += half;
-    len -= half;
+  // wide nodes: at most ceil(24 / 8) = 3 levels below a root of >= 8 bits
+  for (int depth = 0; depth < 3; ++depth) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < R; ++k) any |= node[k] != kNone;
+    if (!__builtin_amdgcn_ballot_w64(any)) break;
+    u32x4 q[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      q[k] = (u32x4){0, kKindLeaf << kKindShift, 0, 0};
+      if (node[k] != kNone) {
+        const uint32_t ns = shift[k] > kNodeStrideMax ? shift[k] - kNodeStrideMax : 0u;
+        const uint32_t idx = (ip[k] >> ns) & ((1u << (shift[k] - ns)) - 1u);
+        q[k] = *(__attribute__((address_space(1))) const u32x4 *)(wide + 4ull * (node[k] + idx));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (node[k] != kNone) {
+        const uint32_t ns = shift[k] > kNodeStrideMax ? shift[k] - kNodeStrideMax : 0u;
+        shift[k] = ns;
+        const uint32_t kind = q[k].y >> kKindShift;
+        node[k] = kNone;
+        if (kind == kKindQuad) site[k] = quad_site(q[k], ip[k] & ((1u << ns) - 1u));
+        else if (kind == kKindLeaf) site[k] = q[k].z;
+        else if (kind == kKindLine) line[k] = q[k].z;
+        else node[k] = q[k].z;
+      }
+    }
   }
-  return vals[off + lo];
+  // leaf lines: position = number of starts 1..7 that are <= ip
+  u32x4 k0[R], k1[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    k0[k] = k1[k] = (u32x4){0, 0, 0, 0};
+    if (line[k] != kNone) {
+      const uint32_t w = line[k] * kLineWords;
+      if (LINES_LDS) {
+        k0[k] = *(const u32x4 *)(s_lines + w);
+        k1[k] = *(const u32x4 *)(s_lines + w + 4);
+      } else {
+        k0[k] = *(__attribute__((address_space(1))) const u32x4 *)(g_lines + w);
+        k1[k] = *(__attribute__((address_space(1))) const u32x4 *)(g_lines + w + 4);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (line[k] != kNone) {
+      const uint32_t x = ip[k];
+      const uint32_t pos = (k0[k].y <= x) + (k0[k].z <= x) + (k0[k].w <= x) + (k1[k].x <= x) +
+                           (k1[k].y <= x) + (k1[k].z <= x) + (k1[k].w <= x);
+      const uint32_t w = line[k] * kLineWords + kLineKeys + pos;
+      site[k] = LINES_LDS ? s_lines[w] : g_lines[w];
+    }
+  }
 }
 
 // floor(b * 8000 / d) for b with 8000*b < 2^53, d >= 1.
@@ -124,6 +202,8 @@ __device__ __forceinline__ uint64_t rate_bps(uint64_t b, uint32_t d) {
 
 __device__ __forceinline__ uint32_t ldg_nt(const uint32_t *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ uint64_t ldg_nt(const uint64_t *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ u32x4 ldg_nt4(const uint32_t *p) { return __builtin_nontemporal_load((const u32x4 *)p); }
+__device__ __forceinline__ u64x2 ldg_nt2(const uint64_t *p) { return __builtin_nontemporal_load((const u64x2 *)p); }
 
 // Window containing record i: largest w with offsets[w] <= i (offsets clamped
 // to [0, n]); also returns the end of that window, at least i + 1.
@@ -143,12 +223,7 @@ __device__ __forceinline__ uint32_t window_of(const ClassifyArgs &a, uint64_t i,
   return lo;
 }
 
-// ---------------------------------------------------------------- kernels
-
-__global__ void init_acc_kernel(u64 *__restrict__ acc, uint64_t words) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < words) acc[i] = ((i & 7u) == 6u) ? ~0ull : 0ull;
-}
+// ---------------------------------------------------------------- accumulation
 
 template <bool ACC_LDS>
 __device__ __forceinline__ void accumulate(u64 *s_acc, u64 *g_row, uint32_t rows, uint32_t row,
@@ -179,11 +254,12 @@ __device__ __forceinline__ void accumulate(u64 *s_acc, u64 *g_row, uint32_t rows
   }
 }
 
-// Flush the workgroup's LDS table into window table g (rows x 8 words) and
-// reset it.  Only touched rows, and only non-empty bulk fields, are sent.
-__device__ __forceinline__ void flush_acc(u64 *s_acc, u64 *__restrict__ g, uint32_t rows) {
+// Flush the workgroup's LDS table into window table g (rows x 8 words) with
+// device-scope atomics and reset it.  Only touched rows, and only non-empty
+// bulk fields, are sent.
+__device__ __forceinline__ void flush_atomic(u64 *s_acc, u64 *__restrict__ g, uint32_t rows) {
   __syncthreads();
-  for (uint32_t r = threadIdx.x; r < rows; r += blockDim.x) {
+  for (uint32_t r = threadIdx.x; r < rows; r += kThreads) {
     const u64 cnt = s_acc[kCnt * rows + r];
     if (cnt == 0) continue;
     u64 *o = g + (uint64_t)r * 8u;
@@ -209,38 +285,150 @@ __device__ __forceinline__ void flush_acc(u64 *s_acc, u64 *__restrict__ g, uint3
   __syncthreads();
 }
 
-template <int R, bool LISTS_LDS, bool ACC_LDS>
+// Copy the workgroup's LDS table (same SoA layout) to its workspace slot and
+// record which window it belongs to.  The kernel ends right after.
+__device__ __forceinline__ void flush_partial(const ClassifyArgs &a, const u64 *s_acc, uint32_t w) {
+  __syncthreads();
+  const uint32_t words = kAccFields * a.rows;
+  u64 *dst = a.ws + (uint64_t)blockIdx.x * words;
+  for (uint32_t i = threadIdx.x; i < words; i += kThreads) dst[i] = s_acc[i];
+  if (threadIdx.x == 0) a.ws_meta[blockIdx.x] = w;
+}
+
+// ---------------------------------------------------------------- record tiles
+
+// R records per lane.  Strided tiles: lane t of a tile at `base` holds records
+// base + k*kThreads + t.  Vector tiles (R = 4): lane t holds base + 4t + k.
+template <int R>
+struct Tile {
+  uint32_t s[R], d[R], pk[R], f[R], l[R];
+  uint64_t b[R];
+  bool v[R];
+};
+
+template <int R>
+__device__ __forceinline__ void clear_tile(Tile<R> &t) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    t.s[k] = t.d[k] = t.pk[k] = t.f[k] = t.l[k] = 0;
+    t.b[k] = 0;
+    t.v[k] = false;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void load_one(Tile<R> &t, int k, const ClassifyArgs &a, uint64_t idx) {
+  t.v[k] = true;
+  t.s[k] = ldg_nt(a.src + idx);
+  t.d[k] = ldg_nt(a.dst + idx);
+  t.b[k] = ldg_nt(a.bytes + idx);
+  t.pk[k] = ldg_nt(a.packets + idx);
+  t.f[k] = ldg_nt(a.first + idx);
+  t.l[k] = ldg_nt(a.last + idx);
+}
+
+template <int R>
+__device__ __forceinline__ void load_strided(Tile<R> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
+  clear_tile(t);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const uint64_t idx = base + (uint64_t)k * kThreads + threadIdx.x;
+    if (idx < end) load_one(t, k, a, idx);
+  }
+}
+
+// Requires base and end multiples of 4 records from a 16-byte aligned start
+// of every field array.
+__device__ __forceinline__ void load_vec(Tile<4> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
+  const uint64_t idx = base + 4ull * threadIdx.x;
+  if (idx < end) {
+    const u32x4 s = ldg_nt4(a.src + idx), d = ldg_nt4(a.dst + idx), pk = ldg_nt4(a.packets + idx);
+    const u32x4 f = ldg_nt4(a.first + idx), l = ldg_nt4(a.last + idx);
+    const u64x2 b0 = ldg_nt2(a.bytes + idx), b1 = ldg_nt2(a.bytes + idx + 2);
+    t.s[0] = s.x; t.s[1] = s.y; t.s[2] = s.z; t.s[3] = s.w;
+    t.d[0] = d.x; t.d[1] = d.y; t.d[2] = d.z; t.d[3] = d.w;
+    t.pk[0] = pk.x; t.pk[1] = pk.y; t.pk[2] = pk.z; t.pk[3] = pk.w;
+    t.f[0] = f.x; t.f[1] = f.y; t.f[2] = f.z; t.f[3] = f.w;
+    t.l[0] = l.x; t.l[1] = l.y; t.l[2] = l.z; t.l[3] = l.w;
+    t.b[0] = b0.x; t.b[1] = b0.y; t.b[2] = b1.x; t.b[3] = b1.y;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t.v[k] = true;
+  } else {
+    clear_tile(t);
+  }
+}
+
+struct Lds {
+  const uint32_t *root, *lmap, *lines;
+  u64 *acc;
+};
+
+template <int R, bool LINES_LDS, bool ACC_LDS>
+__device__ __forceinline__ void process_tile(const Tile<R> &t, const ClassifyArgs &a, const Lds &L,
+                                             u64 *g_tab) {
+  const uint32_t rows = a.rows;
+  uint32_t remote[R], site[R];
+  bool one[R], inbound[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const bool ls = is_local(L.lmap, a.local, t.s[k]);
+    const bool ld = is_local(L.lmap, a.local, t.d[k]);
+    one[k] = t.v[k] && ls != ld;
+    inbound[k] = ld;
+    remote[k] = ld ? t.s[k] : t.d[k];
+  }
+  lookup_sites<R, LINES_LDS>(remote, one, site, L.root, a.wide, L.lines, a.lines, a.root_bits);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (!t.v[k]) continue;
+    const uint32_t row = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
+    const uint32_t dur = t.l[k] - t.f[k];
+    const bool bulk = t.b[k] > a.bulk_bytes && dur > 0u;
+    uint64_t rate = 0;
+    if (bulk) rate = rate_bps(t.b[k], dur);
+    accumulate<ACC_LDS>(L.acc, g_tab, rows, row, t.b[k], t.pk[k], dur, bulk, rate);
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void init_acc_kernel(u64 *__restrict__ acc, uint64_t words) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) acc[i] = ((i & 7u) == 6u) ? ~0ull : 0ull;
+}
+
+template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS>
 __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint32_t *s_root = (uint32_t *)lds;
+  uint32_t *s_lmap = (uint32_t *)(lds + a.lds_off_lmap);
   u64 *s_acc = (u64 *)(lds + a.lds_off_acc);
-  uint32_t *s_keys = (uint32_t *)(lds + a.lds_off_keys);
-  uint32_t *s_vals = (uint32_t *)(lds + a.lds_off_vals);
+  uint32_t *s_lines = (uint32_t *)(lds + a.lds_off_lines);
   const uint32_t tid = threadIdx.x;
   const uint32_t rows = a.rows;
 
-  // stage the trie top (and the leaf lists when they fit) into LDS
+  // stage the trie root, the locality map and (when they fit) the leaf lines
   const uint32_t nroot = 1u << a.root_bits;
   for (uint32_t i = tid; i < nroot; i += kThreads) s_root[i] = a.root[i];
-  if (LISTS_LDS) {
-    for (uint32_t i = tid; i < a.n_list; i += kThreads) {
-      s_keys[i] = a.keys[i];
-      s_vals[i] = a.vals[i];
-    }
-  }
-  if (ACC_LDS) {
-    for (uint32_t r = tid; r < rows; r += kThreads) {
-      for (uint32_t f = 0; f < kAccFields; ++f) s_acc[f * rows + r] = (f == kRateMin) ? ~0ull : 0ull;
-    }
-  }
+  for (uint32_t i = tid; i < kLocalMapWords; i += kThreads) s_lmap[i] = a.lmap[i];
+  if (LINES_LDS)
+    for (uint32_t i = tid; i < a.n_line_words; i += kThreads) s_lines[i] = a.lines[i];
+  if (ACC_LDS)
+    for (uint32_t i = tid; i < kAccFields * rows; i += kThreads) s_acc[i] = (i / rows == kRateMin) ? ~0ull : 0ull;
   __syncthreads();
-  const uint32_t *keys = LISTS_LDS ? s_keys : a.keys;
-  const uint32_t *vals = LISTS_LDS ? s_vals : a.vals;
-  const uint32_t nodir = rows - 1u;
+  const Lds L{s_root, s_lmap, s_lines, s_acc};
 
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
   const uint64_t hi = (uint64_t)(blockIdx.x + 1) * a.n / gridDim.x;
+  if (lo == hi) {
+    // empty slice: leave an empty table whose window keeps the slots ordered
+    if (ACC_LDS && a.ws) {
+      uint64_t we;
+      flush_partial(a, s_acc, window_of(a, lo ? lo - 1 : 0, we));
+    }
+    return;
+  }
   uint64_t i = lo;
   while (i < hi) {
     uint64_t wend;
@@ -249,43 +437,108 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     if (seg_end - i > kMaxRecordsPerFlush) seg_end = i + kMaxRecordsPerFlush;
     u64 *g_tab = a.acc + (uint64_t)w * rows * 8u;
 
-    for (uint64_t base = i; base < seg_end; base += (uint64_t)kThreads * R) {
-      uint32_t s[R], d[R], pk[R], f[R], l[R];
-      uint64_t b[R];
-      bool v[R];
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const uint64_t idx = base + (uint64_t)k * kThreads + tid;
-        v[k] = idx < seg_end;
-        if (v[k]) {
-          s[k] = ldg_nt(a.src + idx);
-          d[k] = ldg_nt(a.dst + idx);
-          b[k] = ldg_nt(a.bytes + idx);
-          pk[k] = ldg_nt(a.packets + idx);
-          f[k] = ldg_nt(a.first + idx);
-          l[k] = ldg_nt(a.last + idx);
+    if (VEC) {
+      // whole groups of 4 records with vector loads; up to 3 records before
+      // and after them in one strided mini-tile
+      const uint64_t a0 = ((i + 3) & ~3ull) < seg_end ? ((i + 3) & ~3ull) : seg_end;
+      const uint64_t a1 = a0 + ((seg_end - a0) & ~3ull);
+      if (i < a0 || a1 < seg_end) {
+        Tile<R> m;
+        clear_tile(m);
+        if (tid < a0 - i) load_one(m, 0, a, i + tid);
+        else if (tid >= 3 && tid - 3 < seg_end - a1) load_one(m, 0, a, a1 + (tid - 3));
+        process_tile<R, LINES_LDS, ACC_LDS>(m, a, L, g_tab);
+      }
+      if (a0 < a1) {
+        constexpr uint64_t T = (uint64_t)kThreads * 4;
+        Tile<4> cur;
+        load_vec(cur, a, a0, a1);
+        for (uint64_t base = a0; base < a1; base += T) {
+          Tile<4> nxt;
+          if (base + T < a1) load_vec(nxt, a, base + T, a1);
+          else clear_tile(nxt);
+          process_tile<4, LINES_LDS, ACC_LDS>(cur, a, L, g_tab);
+          cur = nxt;
         }
       }
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        if (!v[k]) continue;
-        const bool ls = is_local(a.local, s[k]);
-        const bool ld = is_local(a.local, d[k]);
-        uint32_t row = nodir;
-        if (ls != ld) {
-          const uint32_t remote = ld ? s[k] : d[k];
-          const uint32_t site = lookup_site<LISTS_LDS>(remote, s_root, a.nodes, keys, vals, a.root_bits);
-          row = 2u * site + (ld ? 0u : 1u);
-        }
-        const uint32_t dur = l[k] - f[k];
-        const bool bulk = b[k] > a.bulk_bytes && dur > 0u;
-        uint64_t rate = 0;
-        if (bulk) rate = rate_bps(b[k], dur);
-        accumulate<ACC_LDS>(s_acc, g_tab, rows, row, b[k], pk[k], dur, bulk, rate);
+    } else {
+      constexpr uint64_t T = (uint64_t)kThreads * R;
+      Tile<R> cur;
+      load_strided(cur, a, i, seg_end);
+      for (uint64_t base = i; base < seg_end; base += T) {
+        Tile<R> nxt;
+        if (base + T < seg_end) load_strided(nxt, a, base + T, seg_end);
+        else clear_tile(nxt);
+        process_tile<R, LINES_LDS, ACC_LDS>(cur, a, L, g_tab);
+        cur = nxt;
       }
     }
-    if (ACC_LDS) flush_acc(s_acc, g_tab, rows);
+    if (ACC_LDS) {
+      if (seg_end >= hi && a.ws) flush_partial(a, s_acc, w);
+      else flush_atomic(s_acc, g_tab, rows);
+    }
     i = seg_end;
+  }
+}
+
+// Combine the workgroups' final tables: workgroup w * row_tiles + x owns
+// kRedRows rows (tile x) of window w and sums, with kRedSubs lanes per row, the slots whose window is w
+// (a contiguous range, since slot windows never decrease).  Adds into acc, or
+// overwrites it when the classify launch left no other contribution.
+__global__ __launch_bounds__(kRedRows *kRedSubs) void reduce_partials_kernel(
+    const u64 *__restrict__ ws, const uint32_t *__restrict__ meta, uint32_t slots, uint32_t rows,
+    u64 *__restrict__ acc, uint32_t row_tiles, uint32_t overwrite) {
+  const uint32_t w = blockIdx.x / row_tiles, tile = blockIdx.x - w * row_tiles;
+  uint32_t b0 = 0, len = slots;  // first slot with meta >= w
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (meta[b0 + half] < w) { b0 += half + 1; len -= half + 1; }
+    else len = half;
+  }
+  uint32_t b1 = b0;
+  len = slots - b0;  // first slot with meta > w
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (meta[b1 + half] <= w) { b1 += half + 1; len -= half + 1; }
+    else len = half;
+  }
+  if (b0 == b1) return;
+  const uint32_t r = tile * kRedRows + (threadIdx.x % kRedRows);
+  const uint32_t sub = threadIdx.x / kRedRows;
+  u64 v[8] = {0, 0, 0, 0, 0, 0, ~0ull, 0};
+  if (r < rows) {
+    const uint64_t words = (uint64_t)kAccFields * rows;
+    for (uint32_t b = b0 + sub; b < b1; b += kRedSubs) {
+      const u64 *p = ws + (uint64_t)b * words + r;
+      const u64 cnt = p[kCnt * rows];
+      v[0] += cnt & 0xFFFFFFFFull;
+      v[4] += cnt >> 32;
+      v[1] += p[kBytes * rows];
+      v[2] += p[kPackets * rows];
+      v[3] += p[kDur * rows];
+      v[5] += p[kRateSum * rows];
+      const u64 mn = p[kRateMin * rows], mx = p[kRateMax * rows];
+      v[6] = mn < v[6] ? mn : v[6];
+      v[7] = mx > v[7] ? mx : v[7];
+    }
+  }
+  __shared__ u64 red[kRedSubs][8][kRedRows];
+  for (int f = 0; f < 8; ++f) red[sub][f][threadIdx.x % kRedRows] = v[f];
+  __syncthreads();
+  if (sub != 0 || r >= rows) return;
+  for (uint32_t s = 1; s < kRedSubs; ++s) {
+    for (int f = 0; f < 6; ++f) v[f] += red[s][f][threadIdx.x];
+    const u64 mn = red[s][6][threadIdx.x], mx = red[s][7][threadIdx.x];
+    v[6] = mn < v[6] ? mn : v[6];
+    v[7] = mx > v[7] ? mx : v[7];
+  }
+  u64 *o = acc + ((uint64_t)w * rows + r) * 8u;
+  if (overwrite) {
+    for (int f = 0; f < 8; ++f) o[f] = v[f];
+  } else {
+    for (int f = 0; f < 6; ++f) o[f] += v[f];
+    o[6] = v[6] < o[6] ? v[6] : o[6];
+    o[7] = v[7] > o[7] ? v[7] : o[7];
   }
 }
 
@@ -313,59 +566,56 @@ int hip_fail(hipError_t e, const char *where) {
   return GNM_E_HIP;
 }
 
-struct DeviceFacts {
-  int cus = 0;
-};
-
-DeviceFacts device_facts(int dev) {
+int device_cus(int dev) {
   static std::mutex mu;
-  static DeviceFacts facts[64];
+  static int cus[64] = {};
   std::lock_guard<std::mutex> g(mu);
-  if (dev < 0 || dev >= 64) return DeviceFacts{256};
-  if (facts[dev].cus == 0) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-    facts[dev].cus = cus;
+  if (dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cus[dev] = c;
   }
-  return facts[dev];
+  return cus[dev];
 }
 
 typedef void (*KernelFn)(const ClassifyArgs);
 
-template <int R, bool L, bool A>
-KernelFn pick3() { return classify_kernel<R, L, A>; }
-
-template <int R>
-KernelFn pick2(bool lists, bool acc) {
-  if (lists) return acc ? pick3<R, true, true>() : pick3<R, true, false>();
-  return acc ? pick3<R, false, true>() : pick3<R, false, false>();
+// variant slot: shape * 4 + lists * 2 + acc; shapes: R=1, R=2, R=4 strided, R=4 vector
+template <int R, bool V>
+KernelFn pick_la(bool lists, bool acc) {
+  if (lists) return acc ? classify_kernel<R, V, true, true> : classify_kernel<R, V, true, false>;
+  return acc ? classify_kernel<R, V, false, true> : classify_kernel<R, V, false, false>;
 }
 
-KernelFn pick(int r, bool lists, bool acc) {
-  switch (r) {
-    case 1: return pick2<1>(lists, acc);
-    case 2: return pick2<2>(lists, acc);
-    case 4: return pick2<4>(lists, acc);
-    default: return pick2<8>(lists, acc);
+KernelFn pick(int shape, bool lists, bool acc) {
+  switch (shape) {
+    case 0: return pick_la<1, false>(lists, acc);
+    case 1: return pick_la<2, false>(lists, acc);
+    case 2: return pick_la<4, false>(lists, acc);
+    default: return pick_la<4, true>(lists, acc);
   }
 }
 
 // Allow every kernel variant the full 160 KB of LDS, once per device.
-hipError_t allow_lds(KernelFn fn, int dev) {
+hipError_t allow_lds(KernelFn fn, int slot, int dev) {
   static std::mutex mu;
-  static bool done[64][32] = {};
-  int slot = -1;
-  for (int r = 0, k = 0; r < 4; ++r)
-    for (int l = 0; l < 2; ++l)
-      for (int c = 0; c < 2; ++c, ++k)
-        if (fn == pick((1 << r), l, c)) slot = k;
+  static bool done[64][16] = {};
   std::lock_guard<std::mutex> g(mu);
-  if (dev >= 0 && dev < 64 && slot >= 0 && done[dev][slot]) return hipSuccess;
+  if (dev >= 0 && dev < 64 && done[dev][slot]) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-  if (e == hipSuccess && dev >= 0 && dev < 64 && slot >= 0) done[dev][slot] = true;
+  if (e == hipSuccess && dev >= 0 && dev < 64) done[dev][slot] = true;
   return e;
 }
+
+uint32_t blocks_per_cu(const gnm_registry *reg) { return reg->lds_bytes <= kLdsMax / 2 ? 2u : 1u; }
+
+uint64_t partial_bytes(const gnm_registry *reg, uint64_t grid) {
+  const uint64_t tables = grid * kAccFields * reg->rows() * 8u;
+  return tables + ((grid * 4u + 255u) & ~255ull);
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 }  // namespace
 }  // namespace gnm
@@ -376,6 +626,12 @@ extern "C" gnm_params gnm_params_default(void) {
   gnm_params p{};
   p.bulk_bytes = 1000000ull;
   return p;
+}
+
+extern "C" uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks) {
+  if (!reg) return 0;
+  const uint64_t grid = grid_blocks ? grid_blocks : (uint64_t)device_cus(reg->device) * blocks_per_cu(reg);
+  return partial_bytes(reg, grid);
 }
 
 extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
@@ -392,14 +648,27 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   }
   const gnm_params p = pp ? *pp : gnm_params_default();
   const uint32_t R = p.records_per_thread ? p.records_per_thread : 4u;
-  if (R != 1 && R != 2 && R != 4 && R != 8) { set_last_error("records_per_thread must be 0,1,2,4,8"); return GNM_E_INVAL; }
+  if (R != 1 && R != 2 && R != 4) { set_last_error("records_per_thread must be 0, 1, 2 or 4"); return GNM_E_INVAL; }
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != reg->device) { set_last_error("registry belongs to another device"); return GNM_E_INVAL; }
 
   const uint64_t rows = reg->rows();
-  if (!(p.flags & GNM_ACCUMULATE)) {
+  const uint64_t resident = (uint64_t)device_cus(dev) * blocks_per_cu(reg);
+  const uint64_t tiles = (rec->n + (uint64_t)kThreads * R - 1) / ((uint64_t)kThreads * R);
+  uint64_t grid = p.grid_blocks ? p.grid_blocks : (tiles < resident ? tiles : resident);
+  if (grid == 0) grid = 1;
+  if (grid > 65535u * 16u) grid = 65535u * 16u;
+  const bool use_ws = rec->n > 0 && reg->acc_in_lds && p.workspace &&
+                      p.workspace_bytes >= partial_bytes(reg, grid) && aligned16(p.workspace);
+  // With one window, a workspace, no accumulation and slices short enough to
+  // need no mid-launch flush, the reduce kernel writes every row of the
+  // table, so it needs no initialisation.
+  const bool overwrite = use_ws && n_windows == 1 && !(p.flags & GNM_ACCUMULATE) &&
+                         (rec->n + grid - 1) / grid <= kMaxRecordsPerFlush;
+
+  if (!(p.flags & GNM_ACCUMULATE) && !overwrite) {
     const uint64_t words = (uint64_t)n_windows * rows * 8u;
     const uint64_t blocks = (words + 255) / 256;
     hipLaunchKernelGGL(init_acc_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, (u64 *)acc, words);
@@ -411,31 +680,39 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   ClassifyArgs a{};
   a.src = rec->src_ip; a.dst = rec->dst_ip; a.bytes = rec->bytes; a.packets = rec->packets;
   a.first = rec->first_ms; a.last = rec->last_ms; a.n = rec->n;
-  a.woff = window_offsets; a.n_windows = n_windows; a.rows = (uint32_t)rows;
+  a.woff = (gu64 *)window_offsets; a.n_windows = n_windows; a.rows = (uint32_t)rows;
   a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
-  a.root = reg->d_root; a.nodes = reg->d_nodes; a.keys = reg->d_keys; a.vals = reg->d_vals;
-  a.root_bits = reg->root_bits; a.n_list = (uint32_t)reg->keys.size();
-  a.lds_off_acc = reg->lds_off_acc; a.lds_off_keys = reg->lds_off_keys; a.lds_off_vals = reg->lds_off_vals;
+  a.root = (gu32 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
+  a.lmap = (gu32 *)reg->d_lmap;
+  a.root_bits = reg->root_bits; a.n_line_words = (uint32_t)reg->lines.size();
+  a.lds_off_lmap = reg->lds_off_lmap; a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
+  if (use_ws) {
+    a.ws = (u64 *)p.workspace;
+    a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);
+  }
   a.local.n = (uint32_t)reg->local_lo.size();
   for (uint32_t j = 0; j < a.local.n; ++j) {
     a.local.lo[j] = reg->local_lo[j];
     a.local.span[j] = reg->local_hi[j] - reg->local_lo[j];
   }
 
-  const DeviceFacts df = device_facts(dev);
-  const uint32_t per_cu = reg->lds_bytes <= kLdsMax / 2 ? 2u : 1u;
-  const uint64_t resident = (uint64_t)df.cus * per_cu;
-  const uint64_t tiles = (rec->n + (uint64_t)kThreads * R - 1) / ((uint64_t)kThreads * R);
-  uint64_t grid = p.grid_blocks ? p.grid_blocks : (tiles < resident ? tiles : resident);
-  if (grid == 0) grid = 1;
-  if (grid > 65535u * 16u) grid = 65535u * 16u;
-
-  KernelFn fn = pick((int)R, reg->lists_in_lds, reg->acc_in_lds);
-  e = allow_lds(fn, dev);
+  const bool vec = R == 4 && aligned16(rec->src_ip) && aligned16(rec->dst_ip) && aligned16(rec->bytes) &&
+                   aligned16(rec->packets) && aligned16(rec->first_ms) && aligned16(rec->last_ms);
+  const int shape = vec ? 3 : (R == 1 ? 0 : (R == 2 ? 1 : 2));
+  KernelFn fn = pick(shape, reg->lines_in_lds, reg->acc_in_lds);
+  e = allow_lds(fn, shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0), dev);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), reg->lds_bytes, stream, a);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
+  if (use_ws) {
+    const uint32_t row_tiles = (uint32_t)((rows + kRedRows - 1) / kRedRows);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)((uint64_t)row_tiles * n_windows)),
+                       dim3(kRedRows * kRedSubs), 0, stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta,
+                       (uint32_t)grid, (uint32_t)rows, (u64 *)acc, row_tiles, overwrite ? 1u : 0u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  }
   return GNM_OK;
 }
 

@@ -99,7 +99,10 @@ std::vector<Interval> resolve(const std::vector<Pfx> &p, uint32_t none) {
 struct Layout {
   const std::vector<Interval> *iv;
   uint32_t list_max;
-  std::vector<uint32_t> nodes, keys, vals;
+  bool root_lines;  // root cells with <= list_max intervals become leaf lines
+  bool quad_ok;     // site codes fit 16 bits
+  std::vector<uint32_t> wide, lines;
+  uint64_t n_wide_nodes = 0;
   bool overflow = false;
 
   // index of the interval containing address a
@@ -113,34 +116,81 @@ struct Layout {
     return lo;
   }
 
-  // Entry for the cell [lo, lo + 2^shift).
-  uint32_t cell(uint64_t lo, uint32_t shift) {
-    const uint64_t hi = lo + ((uint64_t)1 << shift) - 1;  // inclusive
-    const size_t i0 = find(lo), i1 = find(hi);
-    const size_t count = i1 - i0 + 1;
+  // the intervals overlapping cell [lo, lo + 2^shift): first index, count
+  size_t span(uint64_t lo, uint32_t shift, size_t &count) const {
+    const size_t i0 = find(lo), i1 = find(lo + ((uint64_t)1 << shift) - 1);
+    count = i1 - i0 + 1;
+    return i0;
+  }
+
+  uint32_t add_line(uint64_t lo, size_t i0, size_t count) {
+    const size_t index = lines.size() / kLineWords;
+    if (index > kPayloadMask) { overflow = true; return 0; }
     const auto &v = *iv;
-    if (count == 1) return make_leaf(v[i0].site);
-    if (count <= list_max) {
-      const size_t off = keys.size();
-      if (off + count > kListOffsetMask + 1ull) { overflow = true; return make_leaf(0); }
-      keys.push_back((uint32_t)lo);
-      vals.push_back(v[i0].site);
-      for (size_t j = i0 + 1; j <= i1; ++j) {
-        keys.push_back(v[j].start);
-        vals.push_back(v[j].site);
-      }
-      return make_list((uint32_t)off, (uint32_t)count);
+    uint32_t key[kLineKeys], site[kLineKeys];
+    for (uint32_t j = 0; j < kLineKeys; ++j) {
+      const size_t src = i0 + (j < count ? j : count - 1);
+      key[j] = j == 0 ? (uint32_t)lo : v[src].start;
+      site[j] = v[src].site;
     }
+    lines.insert(lines.end(), key, key + kLineKeys);
+    lines.insert(lines.end(), site, site + kLineKeys);
+    return (uint32_t)index;
+  }
+
+  // 32-bit root entry for the cell [lo, lo + 2^shift)
+  uint32_t root_cell(uint64_t lo, uint32_t shift) {
+    size_t count;
+    const size_t i0 = span(lo, shift, count);
+    if (count == 1) return make_leaf((*iv)[i0].site);
+    if (root_lines && count <= list_max) return make_line(add_line(lo, i0, count));
+    return make_node(wide_node(lo, shift));
+  }
+
+  // wide node for the cell [lo, lo + 2^shift): returns its first entry index
+  uint32_t wide_node(uint64_t lo, uint32_t shift) {
     const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
     const uint32_t stride = shift - ns;
-    const size_t base = nodes.size();
-    if (base + ((size_t)1 << stride) > kPayloadMask) { overflow = true; return make_leaf(0); }
-    nodes.resize(base + ((size_t)1 << stride));
+    const size_t base = wide.size() / 4;
+    if (base + ((size_t)1 << stride) > kPayloadMask) { overflow = true; return 0; }
+    wide.resize(wide.size() + 4 * ((size_t)1 << stride));
+    ++n_wide_nodes;
     for (uint64_t c = 0; c < ((uint64_t)1 << stride); ++c) {
-      const uint32_t e = cell(lo + (c << ns), ns);
-      nodes[base + c] = e;
+      uint32_t q[4];
+      wide_entry(lo + (c << ns), ns, q);
+      for (int j = 0; j < 4; ++j) wide[(base + c) * 4 + j] = q[j];
     }
-    return make_node((uint32_t)base);
+    return (uint32_t)base;
+  }
+
+  // 16-byte wide-node entry for the cell [lo, lo + 2^shift)
+  void wide_entry(uint64_t lo, uint32_t shift, uint32_t q[4]) {
+    size_t count;
+    const size_t i0 = span(lo, shift, count);
+    const auto &v = *iv;
+    q[0] = q[1] = q[2] = q[3] = 0;
+    if (count == 1) {
+      q[1] = kKindLeaf << kKindShift;
+      q[2] = v[i0].site;
+    } else if (count <= 4 && quad_ok && shift <= 16) {
+      uint32_t k[4], st[4];
+      for (uint32_t j = 0; j < 4; ++j) {
+        const size_t src = i0 + (j < count ? j : count - 1);
+        k[j] = j == 0 ? 0u : (uint32_t)(v[src].start - lo);
+        st[j] = v[src].site;
+      }
+      q[0] = k[1] | (k[2] << 16);
+      q[1] = k[3] | (kKindQuad << kKindShift);
+      q[2] = st[0] | (st[1] << 16);
+      q[3] = st[2] | (st[3] << 16);
+    } else if (count <= list_max) {
+      q[1] = kKindLine << kKindShift;
+      q[2] = add_line(lo, i0, count);
+    } else {
+      const uint32_t child = wide_node(lo, shift);
+      q[1] = kKindNode << kKindShift;
+      q[2] = child;
+    }
   }
 };
 
@@ -151,50 +201,86 @@ int fail(int code, const char *msg) {
 
 }  // namespace
 
+uint32_t line_site(const gnm_registry *r, uint32_t index, uint32_t ip) {
+  const uint32_t *line = &r->lines[(size_t)index * kLineWords];
+  uint32_t pos = 0;
+  for (uint32_t j = 1; j < kLineKeys; ++j) pos += line[j] <= ip ? 1u : 0u;
+  return line[kLineKeys + pos];
+}
+
 // Walk of the host copy; mirrors the device walk in kernels.hip.
 uint32_t host_lookup(const gnm_registry *r, uint32_t ip) {
   uint32_t shift = 32u - r->root_bits;
-  uint32_t e = r->root[ip >> shift];
-  while ((e >> kKindShift) == kKindNode) {
+  const uint32_t e = r->root[ip >> shift];
+  if ((e >> kKindShift) == kKindLeaf) return e & kPayloadMask;
+  if ((e >> kKindShift) == kKindLine) return line_site(r, e & kPayloadMask, ip);
+  uint32_t base = e & kPayloadMask;
+  for (;;) {
     const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
     const uint32_t idx = (ip >> ns) & ((1u << (shift - ns)) - 1u);
-    e = r->nodes[(e & kPayloadMask) + idx];
+    const uint32_t *q = &r->wide[((size_t)base + idx) * 4];
     shift = ns;
+    switch (q[1] >> kKindShift) {
+      case kKindLeaf: return q[2];
+      case kKindLine: return line_site(r, q[2], ip);
+      case kKindQuad: {
+        const uint32_t off = ip & (uint32_t)(((uint64_t)1 << ns) - 1);
+        const uint32_t pos = ((q[0] & 0xFFFFu) <= off) + ((q[0] >> 16) <= off) + ((q[1] & 0xFFFFu) <= off);
+        const uint32_t sites[4] = {q[2] & 0xFFFFu, q[2] >> 16, q[3] & 0xFFFFu, q[3] >> 16};
+        return sites[pos];
+      }
+      default: base = q[2];
+    }
   }
-  if ((e >> kKindShift) == kKindLeaf) return e & kPayloadMask;
-  const uint32_t off = e & kListOffsetMask;
-  uint32_t len = ((e >> kListOffsetBits) & 63u) + 1u;
-  uint32_t lo = 0;
-  while (len > 1) {
-    const uint32_t half = len >> 1;
-    if (r->keys[off + lo + half] <= ip) lo += half;
-    len -= half;
-  }
-  return r->vals[off + lo];
 }
 
-bool host_is_local(const gnm_registry *r, uint32_t ip) {
+bool host_in_ranges(const gnm_registry *r, uint32_t ip) {
   for (size_t j = 0; j < r->local_lo.size(); ++j)
     if (ip - r->local_lo[j] <= r->local_hi[j] - r->local_lo[j]) return true;
   return false;
 }
 
-// LDS plan for a classify workgroup: root, then (if they fit) the leaf lists,
-// then (if it fits) the accumulator table.
+// Locality through the /16 map, as the device decides it.
+bool host_is_local(const gnm_registry *r, uint32_t ip) {
+  const uint32_t code = (r->lmap[ip >> 20] >> ((ip >> 15) & 30u)) & 3u;
+  return code == kLocalFull || (code == kLocalPart && host_in_ranges(r, ip));
+}
+
+// 2 bits per /16 block: none, full or partial.  The ranges are disjoint and
+// coalesced, so a block is fully local only if one range covers all of it.
+void build_local_map(gnm_registry *r) {
+  r->lmap.assign(kLocalMapWords, 0u);
+  for (size_t j = 0; j < r->local_lo.size(); ++j) {
+    const uint32_t lo = r->local_lo[j], hi = r->local_hi[j];
+    for (uint64_t b = lo >> 16; b <= (hi >> 16); ++b) {
+      const uint64_t blo = b << 16, bhi = blo | 0xFFFFu;
+      const bool full = lo <= blo && hi >= bhi;
+      const uint32_t sh = (uint32_t)(b & 15u) * 2u;
+      uint32_t &w = r->lmap[b >> 4];
+      const uint32_t cur = (w >> sh) & 3u;
+      const uint32_t code = (full || cur == kLocalFull) ? kLocalFull : kLocalPart;
+      w = (w & ~(3u << sh)) | (code << sh);
+    }
+  }
+}
+
+// LDS plan for a classify workgroup: root and local map, then (if it fits)
+// the accumulator table, then (if they fit) the leaf lines.
 void plan_lds(gnm_registry *r, uint32_t lds_budget) {
   const uint64_t root_b = 4ull << r->root_bits;
-  const uint64_t list_b = 4ull * r->keys.size();
+  const uint64_t lmap_b = 4ull * kLocalMapWords;
+  const uint64_t line_b = 4ull * r->lines.size();
   const uint64_t acc_b = 8ull * kAccFields * r->rows();
-  uint64_t used = root_b;
+  uint64_t used = root_b + lmap_b;
   r->acc_in_lds = used + acc_b <= lds_budget;
   if (r->acc_in_lds) used += acc_b;
-  r->lists_in_lds = used + 2 * list_b <= lds_budget;
-  // layout order: root | acc | keys | vals  (acc 8-byte aligned right after root)
-  r->lds_off_acc = (uint32_t)root_b;
-  uint64_t off = root_b + (r->acc_in_lds ? acc_b : 0);
-  r->lds_off_keys = (uint32_t)off;
-  r->lds_off_vals = (uint32_t)(off + (r->lists_in_lds ? list_b : 0));
-  r->lds_bytes = (uint32_t)(off + (r->lists_in_lds ? 2 * list_b : 0));
+  used = (used + 15u) & ~15ull;  // 16-byte loads of line keys
+  r->lines_in_lds = used + line_b <= lds_budget;
+  // layout: root | lmap | acc | lines   (all offsets multiples of 16 bytes)
+  r->lds_off_lmap = (uint32_t)root_b;
+  r->lds_off_acc = (uint32_t)(root_b + lmap_b);
+  r->lds_off_lines = (uint32_t)used;
+  r->lds_bytes = (uint32_t)(used + (r->lines_in_lds ? line_b : 0));
 }
 
 }  // namespace gnm
@@ -213,12 +299,12 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   gnm_registry_opts o{};
   if (opts) o = *opts;
   const uint32_t root_bits = o.root_bits ? o.root_bits : 12u;
-  const uint32_t list_max = o.list_max ? o.list_max : 16u;
+  const uint32_t list_max = o.list_max ? o.list_max : kLineKeys;
   const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsMax;
   if (root_bits < 8 || root_bits > 15) return fail(GNM_E_INVAL, "root_bits must be 8..15");
-  if (list_max < 2 || list_max > kListCountMax) return fail(GNM_E_INVAL, "list_max must be 2..64");
-  if (lds_budget > kLdsMax || lds_budget < (4u << root_bits))
-    return fail(GNM_E_INVAL, "lds_bytes cannot hold the root table");
+  if (list_max < 2 || list_max > kLineKeys) return fail(GNM_E_INVAL, "list_max must be 2..8");
+  if (lds_budget > kLdsMax || lds_budget < (4u << root_bits) + 4u * kLocalMapWords)
+    return fail(GNM_E_INVAL, "lds_bytes cannot hold the root table and local map");
 
   gnm_registry *r = new (std::nothrow) gnm_registry();
   if (!r) return fail(GNM_E_NOMEM, "host allocation failed");
@@ -273,29 +359,31 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
       return fail(GNM_E_UNSUPPORTED, "local set needs more than 32 disjoint ranges");
     }
 
-    // longest-prefix-match intervals and the trie layout
+    // longest-prefix-match intervals and the trie layout.  Root cells of up
+    // to list_max intervals become leaf lines when all lines fit in LDS
+    // beside the root, locality map and accumulator table; otherwise every
+    // multi-interval root cell gets a wide node (one 16-byte read resolves
+    // most lookups).
     const std::vector<Interval> iv = resolve(d, n_sites);
     r->info.n_intervals = iv.size();
-    Layout lay{&iv, list_max, {}, {}, {}};
-    r->root.resize((size_t)1 << root_bits);
-    for (uint64_t b = 0; b < ((uint64_t)1 << root_bits); ++b) {
-      const uint32_t e = lay.cell(b << (32 - root_bits), 32 - root_bits);
-      r->root[b] = e;
+    build_local_map(r);
+    const bool force_wide = (o.flags & GNM_REG_FORCE_WIDE) != 0;
+    const bool force_lines = (o.flags & GNM_REG_FORCE_LINES) != 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      Layout lay{&iv, list_max, !force_wide && attempt == 0, n_sites < 0xFFFFu, {}, {}};
+      r->root.assign((size_t)1 << root_bits, 0u);
+      for (uint64_t b = 0; b < ((uint64_t)1 << root_bits); ++b) {
+        const uint32_t e = lay.root_cell(b << (32 - root_bits), 32 - root_bits);
+        r->root[b] = e;
+      }
+      if (lay.overflow) { delete r; return fail(GNM_E_NOMEM, "lookup structure exceeds its index range"); }
+      r->wide.swap(lay.wide);
+      r->lines.swap(lay.lines);
+      r->info.n_nodes = lay.n_wide_nodes;
+      plan_lds(r, lds_budget);
+      if (!lay.root_lines || force_lines || r->lines_in_lds) break;
     }
-    if (lay.overflow) { delete r; return fail(GNM_E_NOMEM, "lookup structure exceeds its index range"); }
-    r->nodes.swap(lay.nodes);
-    r->keys.swap(lay.keys);
-    r->vals.swap(lay.vals);
-    r->info.n_nodes = r->nodes.size() ? 0 : 0;
-    {
-      // count node blocks by walking NODE entries
-      uint64_t nn = 0;
-      for (uint32_t e : r->root) nn += (e >> kKindShift) == kKindNode;
-      for (uint32_t e : r->nodes) nn += (e >> kKindShift) == kKindNode;
-      r->info.n_nodes = nn;
-    }
-    r->info.n_list_entries = r->keys.size();
-    plan_lds(r, lds_budget);
+    r->info.n_leaf_lines = r->lines.size() / kLineWords;
   } catch (const std::bad_alloc &) {
     delete r;
     return fail(GNM_E_NOMEM, "host allocation failed");
@@ -305,7 +393,7 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   r->info.n_local_ranges = (uint32_t)r->local_lo.size();
   r->info.root_bits = r->root_bits;
   r->info.list_max = r->list_max;
-  r->info.lists_in_lds = r->lists_in_lds;
+  r->info.lines_in_lds = r->lines_in_lds;
   r->info.acc_in_lds = r->acc_in_lds;
   r->info.lds_bytes = r->lds_bytes;
 
@@ -314,12 +402,12 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
     return GNM_OK;
   }
 
-  // device upload: root | nodes | keys | vals, each 256-byte aligned
+  // device upload: root | wide | lines | lmap, each 256-byte aligned
   auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
-  const uint64_t b_root = 4ull * r->root.size(), b_nodes = 4ull * r->nodes.size();
-  const uint64_t b_keys = 4ull * r->keys.size(), b_vals = 4ull * r->vals.size();
-  const uint64_t o_nodes = al(b_root), o_keys = o_nodes + al(b_nodes), o_vals = o_keys + al(b_keys);
-  const uint64_t total = o_vals + al(b_vals) + 256;
+  const uint64_t b_root = 4ull * r->root.size(), b_nodes = 4ull * r->wide.size();
+  const uint64_t b_lines = 4ull * r->lines.size(), b_lmap = 4ull * r->lmap.size();
+  const uint64_t o_nodes = al(b_root), o_lines = o_nodes + al(b_nodes), o_lmap = o_lines + al(b_lines);
+  const uint64_t total = o_lmap + al(b_lmap) + 256;
   hipError_t e = hipGetDevice(&r->device);
   if (e == hipSuccess) e = hipMalloc(&r->d_buf, total);
   if (e != hipSuccess) {
@@ -329,13 +417,13 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   }
   char *base = (char *)r->d_buf;
   r->d_root = (const uint32_t *)base;
-  r->d_nodes = (const uint32_t *)(base + o_nodes);
-  r->d_keys = (const uint32_t *)(base + o_keys);
-  r->d_vals = (const uint32_t *)(base + o_vals);
+  r->d_wide = (const uint32_t *)(base + o_nodes);
+  r->d_lines = (const uint32_t *)(base + o_lines);
+  r->d_lmap = (const uint32_t *)(base + o_lmap);
   r->d_bytes = total;
   struct Part { const void *h; void *d; uint64_t b; } parts[] = {
-      {r->root.data(), (void *)r->d_root, b_root}, {r->nodes.data(), (void *)r->d_nodes, b_nodes},
-      {r->keys.data(), (void *)r->d_keys, b_keys}, {r->vals.data(), (void *)r->d_vals, b_vals}};
+      {r->root.data(), (void *)r->d_root, b_root}, {r->wide.data(), (void *)r->d_wide, b_nodes},
+      {r->lines.data(), (void *)r->d_lines, b_lines}, {r->lmap.data(), (void *)r->d_lmap, b_lmap}};
   for (const Part &q : parts) {
     if (q.b == 0) continue;
     e = hipMemcpyAsync(q.d, q.h, q.b, hipMemcpyHostToDevice, stream);

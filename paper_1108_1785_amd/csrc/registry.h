@@ -15,9 +15,10 @@ struct gnm_registry {
   uint32_t list_max = 0;
 
   // host copy of the lookup structure (see gnm_internal.h)
-  std::vector<uint32_t> root, nodes, keys, vals;
-  // local set as disjoint inclusive ranges [lo, hi], sorted
+  std::vector<uint32_t> root, wide, lines;
+  // local set as disjoint inclusive ranges [lo, hi], sorted, and its /16 map
   std::vector<uint32_t> local_lo, local_hi;
+  std::vector<uint32_t> lmap;
 
   gnm_registry_info info{};
 
@@ -25,13 +26,13 @@ struct gnm_registry {
   bool host_only = true;
   int device = -1;
   void *d_buf = nullptr;
-  const uint32_t *d_root = nullptr, *d_nodes = nullptr, *d_keys = nullptr, *d_vals = nullptr;
+  const uint32_t *d_root = nullptr, *d_wide = nullptr, *d_lines = nullptr, *d_lmap = nullptr;
   uint64_t d_bytes = 0;
 
   // launch-time LDS plan
-  bool lists_in_lds = false;
+  bool lines_in_lds = false;
   bool acc_in_lds = false;
-  uint32_t lds_off_keys = 0, lds_off_vals = 0, lds_off_acc = 0, lds_bytes = 0;
+  uint32_t lds_off_lmap = 0, lds_off_acc = 0, lds_off_lines = 0, lds_bytes = 0;
 
   uint64_t rows() const { return 2ull * (n_sites + 1ull) + 1ull; }
 };

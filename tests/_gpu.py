@@ -21,18 +21,27 @@ def offsets_to_device(off, device=DEV):
 
 
 def run(reg, rec, window_offsets=None, bulk_bytes=1_000_000, acc=None, accumulate=False,
-        records_per_thread=0, grid_blocks=0, dev_rec=None):
+        records_per_thread=0, grid_blocks=0, dev_rec=None, workspace=None, shift=0):
+    """shift > 0 offsets every field pointer by that many records (misaligned views)."""
     """Classify/aggregate a host Records run on the GPU; returns uint64 [n_windows?, rows, 8]."""
     import torch
     off = window_offsets if window_offsets is not None else rec.window_offsets
     nw = 1 if off is None else len(off) - 1
-    d = dev_rec if dev_rec is not None else to_device(rec)
+    if dev_rec is not None:
+        d = dev_rec
+    elif shift:
+        import flowgen
+        pad = flowgen.concat([rec.slice(0, shift), rec]) if rec.n >= shift else None
+        full = to_device(pad)
+        d = {f: t[shift:] for f, t in full.items()}
+    else:
+        d = to_device(rec)
     if acc is None:
         acc = torch.empty((nw, reg.rows, 8), dtype=torch.int64, device=DEV)
     doff = None if off is None else offsets_to_device(off)
     gnm.classify_aggregate(reg, d, acc, window_offsets=doff, n_windows=nw, bulk_bytes=bulk_bytes,
                            accumulate=accumulate, records_per_thread=records_per_thread,
-                           grid_blocks=grid_blocks, n=rec.n)
+                           grid_blocks=grid_blocks, n=rec.n, workspace=workspace)
     torch.cuda.synchronize()
     out = gnm.acc_to_numpy(acc)
     return out[0] if off is None else out

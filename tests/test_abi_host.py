@@ -67,12 +67,15 @@ def test_worked_example_host_lookup():
     assert loc.tolist() == [True, False, False]
 
 
-@pytest.mark.parametrize("root_bits,list_max", [(8, 2), (8, 64), (12, 16), (15, 2), (15, 64), (10, 3)])
+@pytest.mark.parametrize("layout", ["lines", "wide"])
+@pytest.mark.parametrize("root_bits,list_max", [(8, 2), (8, 8), (12, 4), (15, 2), (15, 8), (10, 3)])
 @pytest.mark.parametrize("seed", range(12))
-def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max):
+def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max, layout):
     rng = np.random.default_rng(1000 + seed)
     n_sites, sites, local = random_tiny_registry(rng, n_prefixes=int(rng.integers(0, 60)))
-    reg = _host_reg(sites, local, n_sites, root_bits=root_bits, list_max=list_max)
+    if layout == "wide" and seed % 3 == 0:
+        n_sites = 70000  # site codes beyond 16 bits: no QUAD entries
+    reg = _host_reg(sites, local, n_sites, root_bits=root_bits, list_max=list_max, layout=layout)
     orc = oracle.Registry([s[0] for s in sites], [s[1] for s in sites], [s[2] for s in sites], n_sites,
                           [x[0] for x in local], [x[1] for x in local])
     pts = np.array(boundary_points(sites + [(a, l, 0) for a, l in local]), dtype=np.uint32)
@@ -81,11 +84,12 @@ def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max):
     assert loc.tolist() == [brute.is_local(local, int(p)) for p in pts.tolist()]
 
 
-def test_host_trie_generated_registries():
+@pytest.mark.parametrize("layout", ["auto", "lines", "wide"])
+def test_host_trie_generated_registries(layout):
     import flowgen
     for wl in (flowgen.PLAIN_SMALL, flowgen.PLAIN_LARGE):
         r = flowgen.registry_for(wl)
-        reg = gnm.Registry.from_generated(r, host_only=True)
+        reg = gnm.Registry.from_generated(r, host_only=True, layout=layout)
         orc = oracle.Registry.from_generated(r)
         pts = boundary_points(list(zip(r.addr.tolist(), r.length.tolist(), r.site.tolist())))
         pts = np.array(pts, dtype=np.uint32)
@@ -120,10 +124,21 @@ def test_registry_errors(sites, n_sites, local, code):
 
 
 def test_build_option_errors():
-    for kw in (dict(root_bits=7), dict(root_bits=16), dict(list_max=1), dict(list_max=65)):
+    for kw in (dict(root_bits=7), dict(root_bits=16), dict(list_max=1), dict(list_max=9)):
         with pytest.raises(gnm.GnmError) as e:
             _host_reg([], [], 1, **kw)
         assert e.value.code == gnm.GNM_E_INVAL
+
+
+def test_workspace_size_formula():
+    reg = _host_reg([(ip("10.0.0.0"), 8, 0)], [], 5)
+    rows = reg.rows
+    assert rows == 2 * 6 + 1
+    for grid in (1, 7, 256):
+        need = grid * 7 * rows * 8 + ((grid * 4 + 255) // 256) * 256
+        assert gnm.workspace_bytes(reg, grid) == need
+    assert gnm.workspace_bytes(reg) >= gnm.workspace_bytes(reg, 1)
+    assert gnm.lib().gnm_workspace_bytes(None, 3) == 0
 
 
 def test_device_calls_reject_host_only_registry_and_nulls():

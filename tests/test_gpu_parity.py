@@ -64,30 +64,64 @@ def _small():
     return _SMALL
 
 
-@pytest.mark.parametrize("rpt", [0, 1, 2, 4, 8])
-def test_plain_small_full(torch_cuda, rpt):
-    say("case: plain-small 100k records, records_per_thread", rpt)
+@pytest.mark.parametrize("rpt", [0, 1, 2, 4])
+@pytest.mark.parametrize("ws", [False, True])
+def test_plain_small_full(torch_cuda, rpt, ws):
+    say("case: plain-small 100k records, records_per_thread", rpt, "workspace", ws)
     s = _small()
     reg = gnm.Registry.from_generated(s["reg"])
     exp = s["orc"].classify_aggregate(s["rec"])
-    got = run(reg, s["rec"], records_per_thread=rpt)
+    got = run(reg, s["rec"], records_per_thread=rpt, workspace=gnm.make_workspace(reg) if ws else None)
     assert (got == exp).all(), diff(got, exp)
     assert (flags(reg, got) == oracle.flags(exp, s["reg"].n_sites)).all()
 
 
-@pytest.mark.parametrize("grid", [1, 3, 64, 256, 1000])
-def test_plain_small_grid_shapes(torch_cuda, grid):
-    say("case: plain-small grid_blocks", grid)
+def test_records_per_thread_8_rejected(torch_cuda):
     s = _small()
     reg = gnm.Registry.from_generated(s["reg"])
-    exp = s["orc"].classify_aggregate(s["rec"])
-    got = run(reg, s["rec"], grid_blocks=grid)
+    with pytest.raises(gnm.GnmError) as e:
+        run(reg, s["rec"].slice(0, 100), records_per_thread=8)
+    assert e.value.code == gnm.GNM_E_INVAL
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3, 5])
+@pytest.mark.parametrize("rpt", [0, 2])
+def test_misaligned_record_views(torch_cuda, shift, rpt):
+    say("case: record pointers offset by", shift, "records, rpt", rpt)
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"].slice(0, 54_321)
+    exp = s["orc"].classify_aggregate(rec)
+    got = run(reg, rec, shift=shift, records_per_thread=rpt, workspace=gnm.make_workspace(reg))
     assert (got == exp).all(), diff(got, exp)
 
 
-@pytest.mark.parametrize("kw", [dict(root_bits=8, list_max=2), dict(root_bits=15, list_max=64),
-                                dict(root_bits=10, list_max=3), dict(lds_bytes=4096 + 256, root_bits=10),
-                                dict(lds_bytes=1024, root_bits=8)])
+@pytest.mark.parametrize("grid", [1, 3, 64, 256, 1000])
+@pytest.mark.parametrize("ws", [False, True])
+def test_plain_small_grid_shapes(torch_cuda, grid, ws):
+    say("case: plain-small grid_blocks", grid, "workspace", ws)
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    exp = s["orc"].classify_aggregate(s["rec"])
+    got = run(reg, s["rec"], grid_blocks=grid, workspace=gnm.make_workspace(reg, grid) if ws else None)
+    assert (got == exp).all(), diff(got, exp)
+
+
+def test_workspace_too_small_falls_back(torch_cuda):
+    import torch
+    say("case: undersized workspace -> atomic merge")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    exp = s["orc"].classify_aggregate(s["rec"])
+    small = torch.empty(64, dtype=torch.uint8, device="cuda:0")
+    got = run(reg, s["rec"], workspace=small)
+    assert (got == exp).all(), diff(got, exp)
+
+
+@pytest.mark.parametrize("kw", [dict(layout="wide"), dict(layout="wide", root_bits=8), dict(layout="lines"),
+                                dict(root_bits=8, list_max=2), dict(root_bits=15, list_max=8),
+                                dict(root_bits=10, list_max=3), dict(lds_bytes=4096 + 16384 + 256, root_bits=10),
+                                dict(lds_bytes=1024 + 16384, root_bits=8)])
 def test_registry_layout_variants(torch_cuda, kw):
     say("case: layout", kw)
     s = _small()
@@ -99,15 +133,16 @@ def test_registry_layout_variants(torch_cuda, kw):
     assert (got == exp).all(), diff(got, exp)
 
 
-@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 1023, 1024, 1025, 4095, 4096, 4097, 8191, 8193, 70001])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 63, 64, 65, 1023, 1024, 1025, 4095, 4096, 4097, 8191, 8193, 70001])
 def test_ragged_sizes(torch_cuda, n):
     say("case: ragged n", n)
     s = _small()
     reg = gnm.Registry.from_generated(s["reg"])
     rec = s["rec"].slice(0, n)
     exp = s["orc"].classify_aggregate(rec)
-    got = run(reg, rec)
-    assert (got == exp).all(), diff(got, exp)
+    for ws in (None, gnm.make_workspace(reg)):
+        got = run(reg, rec, workspace=ws)
+        assert (got == exp).all(), diff(got, exp)
 
 
 def test_edge_registries_and_records(torch_cuda):
@@ -119,11 +154,13 @@ def test_edge_registries_and_records(torch_cuda):
                                                      n_local=int(rng.integers(0, 4)))
         recs = _edge_records(rng, int(rng.integers(0, 3000)), sites, local)
         bulk = int(rng.choice([0, 1_000_000, 1 << 40]))
-        kw = dict(root_bits=int(rng.integers(8, 16)), list_max=int(rng.integers(2, 65)))
+        kw = dict(root_bits=int(rng.integers(8, 16)), list_max=int(rng.integers(2, 9)),
+                  layout=str(rng.choice(["auto", "wide", "lines"])))
         reg, orc = _regs(sites, local, n_sites, **kw)
         rec = soa(recs)
         exp = orc.classify_aggregate(rec, bulk)
-        got = run(reg, rec, bulk_bytes=bulk, records_per_thread=int(rng.choice([1, 2, 4, 8])))
+        got = run(reg, rec, bulk_bytes=bulk, records_per_thread=int(rng.choice([0, 1, 2, 4])),
+                  workspace=gnm.make_workspace(reg) if seed % 2 else None)
         assert (got == exp).all(), (seed, diff(got, exp))
         if seed < 5:
             assert got.tolist() == brute.classify_aggregate(sites, local, n_sites, recs, bulk)
@@ -207,10 +244,11 @@ def test_accumulate_flag(torch_cuda):
     reg = gnm.Registry.from_generated(s["reg"])
     rec = s["rec"]
     exp = s["orc"].classify_aggregate(rec)
-    acc = torch.empty((1, reg.rows, 8), dtype=torch.int64, device="cuda:0")
-    run(reg, rec.slice(0, 40_000), acc=acc)
-    got = run(reg, rec.slice(40_000, rec.n), acc=acc, accumulate=True)
-    assert (got == exp).all(), diff(got, exp)
+    for ws in (None, gnm.make_workspace(reg)):
+        acc = torch.empty((1, reg.rows, 8), dtype=torch.int64, device="cuda:0")
+        run(reg, rec.slice(0, 40_000), acc=acc, workspace=ws)
+        got = run(reg, rec.slice(40_000, rec.n), acc=acc, accumulate=True, workspace=ws)
+        assert (got == exp).all(), diff(got, exp)
 
 
 def test_deterministic_repeats(torch_cuda):
@@ -234,9 +272,10 @@ def test_batched_windows(torch_cuda):
     orc = oracle.Registry.from_generated(r)
     exp = orc.classify_aggregate(rec)
     reg = gnm.Registry.from_generated(r)
-    for rpt, grid in ((0, 0), (8, 0), (1, 37), (4, 2000)):
-        say("  rpt", rpt, "grid", grid)
-        got = run(reg, rec, records_per_thread=rpt, grid_blocks=grid)
+    for rpt, grid, ws in ((0, 0, False), (0, 0, True), (2, 0, True), (1, 37, True), (4, 2000, True), (4, 2000, False)):
+        say("  rpt", rpt, "grid", grid, "workspace", ws)
+        got = run(reg, rec, records_per_thread=rpt, grid_blocks=grid,
+                  workspace=gnm.make_workspace(reg, grid) if ws else None)
         assert (got == exp).all(), diff(got, exp)
     fexp = oracle.flags(exp, r.n_sites)
     assert (flags(reg, got) == fexp).all()
@@ -251,9 +290,24 @@ def test_batched_with_empty_windows(torch_cuda):
     off = np.array(cuts, dtype=np.uint64)
     exp = s["orc"].classify_aggregate(rec, window_offsets=off)
     for grid in (0, 1, 7, 300):
-        got = run(reg, rec, window_offsets=off, grid_blocks=grid)
-        assert (got == exp).all(), diff(got, exp)
+        for ws in (None, gnm.make_workspace(reg, grid)):
+            got = run(reg, rec, window_offsets=off, grid_blocks=grid, workspace=ws)
+            assert (got == exp).all(), diff(got, exp)
     assert (got[0, :, 6] == np.uint64(M64)).all() and (got[0, :, 0] == 0).all()
+
+
+def test_sites_beyond_16_bits(torch_cuda):
+    say("case: 70000 sites (no 16-bit site codes)")
+    rng = np.random.default_rng(77)
+    from tests.test_oracle_pins import _edge_records
+    _, sites, local = random_tiny_registry(rng, n_prefixes=50, n_local=2)
+    sites = [(a, l, (s * 13331) % 70000) for a, l, s in sites]
+    recs = _edge_records(rng, 3000, sites, local)
+    for layout in ("wide", "lines"):
+        reg, orc = _regs(sites, local, 70000, layout=layout)
+        exp = orc.classify_aggregate(soa(recs))
+        got = run(reg, soa(recs))
+        assert (got == exp).all(), diff(got, exp)
 
 
 def test_plain_large_full_size(torch_cuda):
@@ -264,6 +318,8 @@ def test_plain_large_full_size(torch_cuda):
     exp = orc.classify_aggregate(rec)
     reg = gnm.Registry.from_generated(r)
     say("  info", reg.info())
-    got = run(reg, rec)
-    assert (got == exp).all(), diff(got, exp)
+    d = to_device(rec)
+    for ws in (gnm.make_workspace(reg), None):
+        got = run(reg, rec, dev_rec=d, workspace=ws)
+        assert (got == exp).all(), diff(got, exp)
     assert (flags(reg, got) == oracle.flags(exp, r.n_sites)).all()
