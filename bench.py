@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 METRIC = "flow records/sec + HBM GB/s (batched vs plain, bit-exact); p99 window latency"
 ALG_BYTES_PER_RECORD = 28  # src_ip, dst_ip, bytes, packets, first_ms, last_ms
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E peak
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_classify_plain_large.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_classify_plain_large.txt")
 
 
 def log(*a):
@@ -49,15 +49,23 @@ def kernel_source_hash() -> str:
 
 
 def load_traffic():
-    """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
+    """HBM bytes per launch from committed rocprofv3 counter runs, if current.
+
+    The summary file holds `key: value` lines; `kernel_source_hash` must match
+    the kernels as built now, else the counters are stale and traffic is null.
+    """
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -70,6 +78,9 @@ def main():
     ap.add_argument("--records-per-thread", type=int, default=0)
     ap.add_argument("--grid-blocks", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--no-workspace", action="store_true", help="merge tables with atomics only")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (scale for FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this path has no multi-GPU launch (records shard with no "
@@ -85,6 +96,14 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     gnm.lib()  # fail loudly if the HIP library is missing
+
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy of %d MiB done" % args.calib_copy_mib)
 
     t_gen = time.time()
     reg_h = flowgen.registry_for(flowgen.PLAIN_LARGE)
@@ -111,16 +130,16 @@ def main():
 
     views = [{f: t[k * n_win:(k + 1) * n_win] for f, t in d.items()} for k in range(args.windows)]
     structs = [gnm.records_struct(v, n_win) for v in views]
-    empty = gnm.RecordsC()
     acc = torch.empty((1, rows, 8), dtype=torch.int64, device=dev)
     flags = torch.empty(n_sites, dtype=torch.uint8, device=dev)
-    kw = dict(records_per_thread=args.records_per_thread, grid_blocks=args.grid_blocks)
+    ws = None if args.no_workspace else gnm.make_workspace(reg, args.grid_blocks, device=dev)
+    kw = dict(records_per_thread=args.records_per_thread, grid_blocks=args.grid_blocks, workspace=ws)
 
     def plain_step(k, ev=None):
-        gnm.classify_aggregate(reg, empty, acc)  # initialise the table
+        # one call: (table initialisation,) classify kernel, (workspace reduce)
         if ev is not None:
             ev[0].record()
-        gnm.classify_aggregate(reg, structs[k], acc, accumulate=True, **kw)
+        gnm.classify_aggregate(reg, structs[k], acc, **kw)
         if ev is not None:
             ev[1].record()
         gnm.flag_suboptimal(reg, acc, 1, flags)
@@ -149,10 +168,9 @@ def main():
     bstruct = gnm.records_struct(d, big.n)
 
     def batched_step(ev=None):
-        gnm.classify_aggregate(reg, empty, acc_b, window_offsets=off_dev, n_windows=nb)
         if ev is not None:
             ev[0].record()
-        gnm.classify_aggregate(reg, bstruct, acc_b, window_offsets=off_dev, n_windows=nb, accumulate=True, **kw)
+        gnm.classify_aggregate(reg, bstruct, acc_b, window_offsets=off_dev, n_windows=nb, **kw)
         if ev is not None:
             ev[1].record()
         gnm.flag_suboptimal(reg, acc_b, nb, flags_b)
@@ -185,12 +203,13 @@ def main():
         import oracle
         orc = oracle.Registry.from_generated(reg_h)
         reps, t_cpu, exp = 0, 0.0, None
-        while reps < 5 and (reps == 0 or t_cpu < 10.0):
+        while reps < 400 and (reps == 0 or t_cpu < 10.0):
             tc = time.perf_counter()
             exp = orc.classify_aggregate(parts[0])
             t_cpu += time.perf_counter() - tc
             reps += 1
-            log("oracle rep %d: %.2fs" % (reps, t_cpu))
+            if reps == 1 or reps % 20 == 0:
+                log("oracle rep %d: %.2fs" % (reps, t_cpu))
         cpu = {"value": reps * n_win / t_cpu, "unit": "records/s", "cores": oracle.max_threads(),
                "kind": "oracle",
                "sample": "%d x one full %d-record plain-large window (OpenMP over records)" % (reps, n_win)}
@@ -226,7 +245,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-            "kernel": "classify_kernel", "kernel_ms_avg": k_avg,
+            "kernel": "classify_kernel + reduce_partials_kernel (one classify call)",
+            "kernel_ms_avg": k_avg,
         },
         "cpu_baseline": cpu,
         "parity": parity,
