@@ -126,7 +126,7 @@ typedef struct {
 /* Registry build options (NULL = defaults). */
 typedef struct {
   uint32_t flags;          /* GNM_REG_HOST_ONLY: no device upload (inspection only) */
-  uint32_t root_bits;      /* 0 = automatic; else 8..15 bits indexed by the LDS-resident top level */
+  uint32_t root_bits;      /* 0 = automatic (12); else 8..14 bits indexed by the LDS-resident top level */
   uint32_t list_max;       /* 0 = automatic (8); else 2..8 intervals per 64-byte leaf line */
   uint32_t lds_bytes;      /* 0 = automatic; LDS budget of the lookup structure */
 } gnm_registry_opts;

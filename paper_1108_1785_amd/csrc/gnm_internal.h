@@ -8,8 +8,12 @@
 // is constant on maximal intervals between prefix starts and ends.  It is laid
 // out as a direct-indexed trie:
 //
-//   root[2^root_bits]   32-bit entries indexed by the top root_bits of the
-//                       address (staged into LDS by every classify workgroup);
+//   root[2^root_bits]   64-bit entries indexed by the top root_bits of the
+//                       address (staged into LDS by every classify workgroup):
+//                       the low word is the trie entry below, the high word
+//                       the locality of the cell's 16 equal sub-blocks (bit j
+//                       = sub-block j entirely local, bit 16 + j = partly
+//                       local, decided by the local ranges);
 //   wide[]              inner nodes: arrays of 16-byte entries indexed by the
 //                       next up-to-8 address bits;
 //   lines[]             leaf lines of 64 bytes for cells holding 2..8
@@ -18,7 +22,7 @@
 //                       slots repeat the last interval, so the answer is
 //                       sites[number of starts 1..7 that are <= address].
 //
-// Root entry (bits 31..30 = kind, bits 29..0 = payload):
+// Root trie entry (bits 31..30 = kind, bits 29..0 = payload):
 //   LEAF (2): site code (site id, or n_sites = no site);
 //   LINE (0): index of the cell's leaf line;
 //   NODE (1): index (in 16-byte entries) of the cell's wide node.
@@ -32,11 +36,10 @@
 //             16-bit codes s0 = z & 0xFFFF, s1 = z >> 16, s2 = w & 0xFFFF,
 //             s3 = w >> 16; unused slots repeat the last interval.
 // A node below a cell that leaves `shift` address bits unresolved indexes
-// min(8, shift) bits; its children then leave shift - that many.
-//
-// Local set: besides the disjoint ranges, a map of 2 bits per /16 block of
-// the address space (4096 words of 16 blocks each): 0 = no local address,
-// 1 = every address local, 2 = partly local (decided by the ranges).
+// min(8, shift) bits; its children then leave shift - that many.  Entry 0 of
+// wide[] and line 0 of lines[] are dummies (site 0) that are never referenced
+// by the trie; lanes with no lookup to do read them instead of branching.
+
 #pragma once
 
 #include <cstdint>
@@ -54,14 +57,14 @@ constexpr uint32_t kLineWords = 16;   // 8 starts + 8 site codes = 64 bytes
 constexpr uint32_t kNodeStrideMax = 8;
 
 constexpr uint32_t kMaxLocalRanges = 32;
-constexpr uint32_t kLocalMapWords = 4096;  // 65536 /16 blocks x 2 bits
-constexpr uint32_t kLocalNone = 0, kLocalFull = 1, kLocalPart = 2;
+constexpr uint32_t kLocalSubBlocks = 16;  // locality sub-blocks per root cell
 constexpr uint32_t kMaxSites = 1u << 28;
 constexpr uint32_t kLdsMax = 160u * 1024u;
 
-// Accumulator table held in LDS by a classify workgroup, structure of arrays
-// of `rows` 64-bit words each.  `cnt` packs flows (low 32 bits) and bulk
-// flows (high 32 bits); a workgroup flushes before either can reach 2^32.
+// Accumulator table held in LDS by a classify workgroup: rows of kAccFields
+// 64-bit words (56 bytes, so rows fall on 32 distinct banks).  `cnt` packs
+// flows (low 32 bits) and bulk flows (high 32 bits); a workgroup flushes
+// before either can reach 2^32.
 enum AccField : uint32_t { kCnt = 0, kBytes, kPackets, kDur, kRateSum, kRateMin, kRateMax, kAccFields };
 
 constexpr uint64_t kMaxRecordsPerFlush = 1ull << 31;

@@ -11,7 +11,8 @@
 //     contiguous slice of the records, streamed with non-temporal 16-byte
 //     loads (4 consecutive records per lane per field), the next tile's loads
 //     in flight while the current tile is classified;
-//   * LDS-resident locality map (2 bits per /16) and trie root, and the trie's
+//   * an LDS-resident trie root whose 64-bit entries also carry the locality
+//     of 16 sub-blocks per cell (one read per endpoint), and the trie's
 //     64-byte leaf lines as well when they fit; otherwise wide inner nodes
 //     whose 16-byte entries usually hold a whole cell, so one cached read
 //     resolves a lookup; the R lookups of a lane advance in lockstep so their
@@ -45,8 +46,8 @@ typedef __attribute__((address_space(1))) const uint32_t gu32;
 typedef __attribute__((address_space(1))) const uint64_t gu64;
 
 constexpr uint32_t kThreads = 1024;
-constexpr uint32_t kRedRows = 16;  // reduce kernel: rows per workgroup
-constexpr uint32_t kRedSubs = 16;  // reduce kernel: partial tables summed in parallel per row
+constexpr uint32_t kRedRows = 8;   // reduce kernel: rows per workgroup
+constexpr uint32_t kRedSubs = 32;  // reduce kernel: partial tables summed in parallel per row
 
 struct LocalRanges {
   uint32_t n;
@@ -64,10 +65,11 @@ struct ClassifyArgs {
   uint32_t rows;
   uint64_t bulk_bytes;
   u64 *acc;  // n_windows * rows * 8 words
-  gu32 *root, *wide, *lines, *lmap;
+  gu64 *root;  // trie entry | locality masks << 32
+  gu32 *wide, *lines;
   uint32_t root_bits;
   uint32_t n_line_words;
-  uint32_t lds_off_lmap, lds_off_acc, lds_off_lines;
+  uint32_t lds_off_acc, lds_off_lines;
   u64 *ws;             // NULL: every table is flushed with atomics
   uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
   LocalRanges local;
@@ -81,76 +83,69 @@ __device__ __forceinline__ bool in_ranges(const LocalRanges &L, uint32_t ip) {
   return r;
 }
 
-// Locality from the LDS /16 map; the ranges decide only partly-local blocks.
-__device__ __forceinline__ bool is_local(const uint32_t *s_lmap, const LocalRanges &L, uint32_t ip) {
-  const uint32_t code = (s_lmap[ip >> 20] >> ((ip >> 15) & 30u)) & 3u;
-  if (code == kLocalPart) return in_ranges(L, ip);
-  return code == kLocalFull;
-}
 
+// Site of offset `off` in a QUAD wide-node entry.
 __device__ __forceinline__ uint32_t quad_site(u32x4 q, uint32_t off) {
   const uint32_t pos = ((q.x & 0xFFFFu) <= off) + ((q.x >> 16) <= off) + ((q.y & 0xFFFFu) <= off);
   const uint32_t lo = pos & 2u ? q.w : q.z;
   return pos & 1u ? lo >> 16 : lo & 0xFFFFu;
 }
 
-// Longest-prefix match of R addresses at once: site codes of the intervals
-// containing ip[k] for lanes with act[k].  The R walks advance in lockstep
+// Longest-prefix match of R addresses at once, from the root trie entries of
+// their cells: site codes of the intervals containing ip[k] for lanes with
+// act[k].  The R walks advance in lockstep
 // so that their memory accesses are in flight together.  A wide-node entry
 // costs one 16-byte read and usually resolves the address; a leaf line costs
-// one 64-byte line fetch (keys) and one read of the same line (site).
+// one 64-byte line read (keys) and one read of the same line (site).  Lanes
+// with nothing to resolve read the dummy entry 0 rather than branching.
 template <int R, bool LINES_LDS>
-__device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const bool (&act)[R],
-                                             uint32_t (&site)[R], const uint32_t *s_root,
-                                             gu32 *wide, const uint32_t *s_lines, gu32 *g_lines,
-                                             uint32_t root_bits) {
-  constexpr uint32_t kNone = 0xFFFFFFFFu;
-  uint32_t node[R], line[R], shift[R];
+__device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint32_t (&root_e)[R],
+                                             const bool (&act)[R], uint32_t (&site)[R], gu32 *wide,
+                                             const uint32_t *s_lines, gu32 *g_lines, uint32_t root_bits) {
+  uint32_t node[R], line[R];
+  bool any = false, any_line = false;
+  // every lane still walking at depth d has the same number of unresolved
+  // address bits, so the shift is wave-uniform
+  uint32_t shift = 32u - root_bits;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    shift[k] = 32u - root_bits;
-    const uint32_t e = act[k] ? s_root[ip[k] >> shift[k]] : (kKindLeaf << kKindShift);
-    const uint32_t kind = e >> kKindShift, pay = e & kPayloadMask;
+    const uint32_t e = root_e[k];
+    const uint32_t kind = act[k] ? e >> kKindShift : kKindLeaf, pay = e & kPayloadMask;
     site[k] = pay;
-    node[k] = kind == kKindNode ? pay : kNone;
-    line[k] = kind == kKindLine ? pay : kNone;
+    node[k] = kind == kKindNode ? pay : 0u;
+    line[k] = kind == kKindLine ? pay : 0u;
+    any |= node[k] != 0u;
+    any_line |= line[k] != 0u;
   }
   // wide nodes: at most ceil(24 / 8) = 3 levels below a root of >= 8 bits
-  for (int depth = 0; depth < 3; ++depth) {
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < R; ++k) any |= node[k] != kNone;
-    if (!__builtin_amdgcn_ballot_w64(any)) break;
+  for (int depth = 0; depth < 3 && __builtin_amdgcn_ballot_w64(any); ++depth) {
+    const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
+    const uint32_t mask = (1u << (shift - ns)) - 1u;
     u32x4 q[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      q[k] = (u32x4){0, kKindLeaf << kKindShift, 0, 0};
-      if (node[k] != kNone) {
-        const uint32_t ns = shift[k] > kNodeStrideMax ? shift[k] - kNodeStrideMax : 0u;
-        const uint32_t idx = (ip[k] >> ns) & ((1u << (shift[k] - ns)) - 1u);
-        q[k] = *(__attribute__((address_space(1))) const u32x4 *)(wide + 4ull * (node[k] + idx));
-      }
+      const uint32_t idx = node[k] ? (ip[k] >> ns) & mask : 0u;
+      q[k] = *(__attribute__((address_space(1))) const u32x4 *)(wide + 4ull * (node[k] + idx));
     }
+    shift = ns;
+    any = false;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      if (node[k] != kNone) {
-        const uint32_t ns = shift[k] > kNodeStrideMax ? shift[k] - kNodeStrideMax : 0u;
-        shift[k] = ns;
-        const uint32_t kind = q[k].y >> kKindShift;
-        node[k] = kNone;
-        if (kind == kKindQuad) site[k] = quad_site(q[k], ip[k] & ((1u << ns) - 1u));
-        else if (kind == kKindLeaf) site[k] = q[k].z;
-        else if (kind == kKindLine) line[k] = q[k].z;
-        else node[k] = q[k].z;
-      }
+      if (!node[k]) continue;
+      const uint32_t kind = q[k].y >> kKindShift;
+      const uint32_t quad = quad_site(q[k], ip[k] & ((1u << ns) - 1u));
+      site[k] = kind == kKindQuad ? quad : q[k].z;
+      line[k] = kind == kKindLine ? q[k].z : 0u;
+      node[k] = kind == kKindNode ? q[k].z : 0u;
+      any |= node[k] != 0u;
+      any_line |= line[k] != 0u;
     }
   }
   // leaf lines: position = number of starts 1..7 that are <= ip
-  u32x4 k0[R], k1[R];
+  if (LINES_LDS || __builtin_amdgcn_ballot_w64(any_line)) {
+    u32x4 k0[R], k1[R];
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    k0[k] = k1[k] = (u32x4){0, 0, 0, 0};
-    if (line[k] != kNone) {
+    for (int k = 0; k < R; ++k) {
       const uint32_t w = line[k] * kLineWords;
       if (LINES_LDS) {
         k0[k] = *(const u32x4 *)(s_lines + w);
@@ -160,15 +155,14 @@ __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const bool
         k1[k] = *(__attribute__((address_space(1))) const u32x4 *)(g_lines + w + 4);
       }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (line[k] != kNone) {
+    for (int k = 0; k < R; ++k) {
       const uint32_t x = ip[k];
       const uint32_t pos = (k0[k].y <= x) + (k0[k].z <= x) + (k0[k].w <= x) + (k1[k].x <= x) +
                            (k1[k].y <= x) + (k1[k].z <= x) + (k1[k].w <= x);
       const uint32_t w = line[k] * kLineWords + kLineKeys + pos;
-      site[k] = LINES_LDS ? s_lines[w] : g_lines[w];
+      const uint32_t ls = LINES_LDS ? s_lines[w] : g_lines[w];
+      if (line[k]) site[k] = ls;
     }
   }
 }
@@ -226,18 +220,18 @@ __device__ __forceinline__ uint32_t window_of(const ClassifyArgs &a, uint64_t i,
 // ---------------------------------------------------------------- accumulation
 
 template <bool ACC_LDS>
-__device__ __forceinline__ void accumulate(u64 *s_acc, u64 *g_row, uint32_t rows, uint32_t row,
-                                           uint64_t b, uint32_t pk, uint32_t dur, bool bulk,
-                                           uint64_t rate) {
+__device__ __forceinline__ void accumulate(u64 *s_acc, u64 *g_row, uint32_t row, uint64_t b, uint32_t pk,
+                                           uint32_t dur, bool bulk, uint64_t rate) {
   if (ACC_LDS) {
-    atomicAdd(&s_acc[kCnt * rows + row], 1ull | ((u64)bulk << 32));
-    atomicAdd(&s_acc[kBytes * rows + row], (u64)b);
-    atomicAdd(&s_acc[kPackets * rows + row], (u64)pk);
-    atomicAdd(&s_acc[kDur * rows + row], (u64)dur);
+    u64 *t = s_acc + row * kAccFields;  // one address, immediate field offsets
+    atomicAdd(&t[kCnt], 1ull | ((u64)bulk << 32));
+    atomicAdd(&t[kBytes], (u64)b);
+    atomicAdd(&t[kPackets], (u64)pk);
+    atomicAdd(&t[kDur], (u64)dur);
     if (bulk) {
-      atomicAdd(&s_acc[kRateSum * rows + row], (u64)rate);
-      atomicMin(&s_acc[kRateMin * rows + row], (u64)rate);
-      atomicMax(&s_acc[kRateMax * rows + row], (u64)rate);
+      atomicAdd(&t[kRateSum], (u64)rate);
+      atomicMin(&t[kRateMin], (u64)rate);
+      atomicMax(&t[kRateMax], (u64)rate);
     }
   } else {
     u64 *g = g_row + (uint64_t)row * 8u;
@@ -260,32 +254,28 @@ __device__ __forceinline__ void accumulate(u64 *s_acc, u64 *g_row, uint32_t rows
 __device__ __forceinline__ void flush_atomic(u64 *s_acc, u64 *__restrict__ g, uint32_t rows) {
   __syncthreads();
   for (uint32_t r = threadIdx.x; r < rows; r += kThreads) {
-    const u64 cnt = s_acc[kCnt * rows + r];
+    u64 *t = s_acc + r * kAccFields;
+    const u64 cnt = t[kCnt];
     if (cnt == 0) continue;
     u64 *o = g + (uint64_t)r * 8u;
     atomicAdd(&o[0], cnt & 0xFFFFFFFFull);
-    atomicAdd(&o[1], s_acc[kBytes * rows + r]);
-    atomicAdd(&o[2], s_acc[kPackets * rows + r]);
-    atomicAdd(&o[3], s_acc[kDur * rows + r]);
+    atomicAdd(&o[1], t[kBytes]);
+    atomicAdd(&o[2], t[kPackets]);
+    atomicAdd(&o[3], t[kDur]);
     const u64 nb = cnt >> 32;
     if (nb) {
       atomicAdd(&o[4], nb);
-      atomicAdd(&o[5], s_acc[kRateSum * rows + r]);
-      atomicMin(&o[6], s_acc[kRateMin * rows + r]);
-      atomicMax(&o[7], s_acc[kRateMax * rows + r]);
+      atomicAdd(&o[5], t[kRateSum]);
+      atomicMin(&o[6], t[kRateMin]);
+      atomicMax(&o[7], t[kRateMax]);
     }
-    s_acc[kCnt * rows + r] = 0;
-    s_acc[kBytes * rows + r] = 0;
-    s_acc[kPackets * rows + r] = 0;
-    s_acc[kDur * rows + r] = 0;
-    s_acc[kRateSum * rows + r] = 0;
-    s_acc[kRateMin * rows + r] = ~0ull;
-    s_acc[kRateMax * rows + r] = 0;
+    t[kCnt] = t[kBytes] = t[kPackets] = t[kDur] = t[kRateSum] = t[kRateMax] = 0;
+    t[kRateMin] = ~0ull;
   }
   __syncthreads();
 }
 
-// Copy the workgroup's LDS table (same SoA layout) to its workspace slot and
+// Copy the workgroup's LDS table (same row layout) to its workspace slot and
 // record which window it belongs to.  The kernel ends right after.
 __device__ __forceinline__ void flush_partial(const ClassifyArgs &a, const u64 *s_acc, uint32_t w) {
   __syncthreads();
@@ -297,96 +287,168 @@ __device__ __forceinline__ void flush_partial(const ClassifyArgs &a, const u64 *
 
 // ---------------------------------------------------------------- record tiles
 
-// R records per lane.  Strided tiles: lane t of a tile at `base` holds records
-// base + k*kThreads + t.  Vector tiles (R = 4): lane t holds base + 4t + k.
+// R records per lane, in two parts loaded at different times: the endpoint
+// addresses (needed first, for locality and the trie walk) and the rest.
+// Strided tiles: lane t of a tile at `base` holds records base + k*kThreads + t.
+// Vector tiles (R = 4): lane t holds base + 4t + k, one 16-byte load per field.
 template <int R>
-struct Tile {
-  uint32_t s[R], d[R], pk[R], f[R], l[R];
-  uint64_t b[R];
+struct Addr {
+  uint32_t s[R], d[R];
   bool v[R];
 };
-
 template <int R>
-__device__ __forceinline__ void clear_tile(Tile<R> &t) {
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    t.s[k] = t.d[k] = t.pk[k] = t.f[k] = t.l[k] = 0;
-    t.b[k] = 0;
-    t.v[k] = false;
-  }
-}
+struct Rest {
+  uint32_t pk[R], f[R], l[R];
+  uint64_t b[R];
+};
 
-template <int R>
-__device__ __forceinline__ void load_one(Tile<R> &t, int k, const ClassifyArgs &a, uint64_t idx) {
-  t.v[k] = true;
-  t.s[k] = ldg_nt(a.src + idx);
-  t.d[k] = ldg_nt(a.dst + idx);
-  t.b[k] = ldg_nt(a.bytes + idx);
-  t.pk[k] = ldg_nt(a.packets + idx);
-  t.f[k] = ldg_nt(a.first + idx);
-  t.l[k] = ldg_nt(a.last + idx);
-}
-
-template <int R>
-__device__ __forceinline__ void load_strided(Tile<R> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
-  clear_tile(t);
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const uint64_t idx = base + (uint64_t)k * kThreads + threadIdx.x;
-    if (idx < end) load_one(t, k, a, idx);
-  }
-}
-
-// Requires base and end multiples of 4 records from a 16-byte aligned start
-// of every field array.
-__device__ __forceinline__ void load_vec(Tile<4> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
-  const uint64_t idx = base + 4ull * threadIdx.x;
-  if (idx < end) {
-    const u32x4 s = ldg_nt4(a.src + idx), d = ldg_nt4(a.dst + idx), pk = ldg_nt4(a.packets + idx);
-    const u32x4 f = ldg_nt4(a.first + idx), l = ldg_nt4(a.last + idx);
-    const u64x2 b0 = ldg_nt2(a.bytes + idx), b1 = ldg_nt2(a.bytes + idx + 2);
+template <int R, bool VEC>
+__device__ __forceinline__ void load_addr(Addr<R> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
+  if (VEC) {
+    const uint64_t idx = base + 4ull * threadIdx.x;
+    const bool ok = idx < end;  // end is base + a multiple of 4
+    u32x4 s = {0, 0, 0, 0}, d = {0, 0, 0, 0};
+    if (ok) {
+      s = ldg_nt4(a.src + idx);
+      d = ldg_nt4(a.dst + idx);
+    }
     t.s[0] = s.x; t.s[1] = s.y; t.s[2] = s.z; t.s[3] = s.w;
     t.d[0] = d.x; t.d[1] = d.y; t.d[2] = d.z; t.d[3] = d.w;
+#pragma unroll
+    for (int k = 0; k < R; ++k) t.v[k] = ok;
+  } else {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint64_t idx = base + (uint64_t)k * kThreads + threadIdx.x;
+      t.v[k] = idx < end;
+      t.s[k] = t.v[k] ? ldg_nt(a.src + idx) : 0u;
+      t.d[k] = t.v[k] ? ldg_nt(a.dst + idx) : 0u;
+    }
+  }
+}
+
+template <int R, bool VEC>
+__device__ __forceinline__ void load_rest(Rest<R> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
+  if (VEC) {
+    const uint64_t idx = base + 4ull * threadIdx.x;
+    u32x4 pk = {0, 0, 0, 0}, f = {0, 0, 0, 0}, l = {0, 0, 0, 0};
+    u64x2 b0 = {0, 0}, b1 = {0, 0};
+    if (idx < end) {
+      pk = ldg_nt4(a.packets + idx);
+      f = ldg_nt4(a.first + idx);
+      l = ldg_nt4(a.last + idx);
+      b0 = ldg_nt2(a.bytes + idx);
+      b1 = ldg_nt2(a.bytes + idx + 2);
+    }
     t.pk[0] = pk.x; t.pk[1] = pk.y; t.pk[2] = pk.z; t.pk[3] = pk.w;
     t.f[0] = f.x; t.f[1] = f.y; t.f[2] = f.z; t.f[3] = f.w;
     t.l[0] = l.x; t.l[1] = l.y; t.l[2] = l.z; t.l[3] = l.w;
     t.b[0] = b0.x; t.b[1] = b0.y; t.b[2] = b1.x; t.b[3] = b1.y;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) t.v[k] = true;
   } else {
-    clear_tile(t);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint64_t idx = base + (uint64_t)k * kThreads + threadIdx.x;
+      const bool ok = idx < end;
+      t.pk[k] = ok ? ldg_nt(a.packets + idx) : 0u;
+      t.f[k] = ok ? ldg_nt(a.first + idx) : 0u;
+      t.l[k] = ok ? ldg_nt(a.last + idx) : 0u;
+      t.b[k] = ok ? ldg_nt(a.bytes + idx) : 0ull;
+    }
+  }
+}
+
+// One record per lane at an arbitrary index (segment heads and tails).
+template <int R>
+__device__ __forceinline__ void load_single(Addr<R> &t, Rest<R> &r, const ClassifyArgs &a, uint64_t idx,
+                                            bool ok) {
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    t.v[k] = false;
+    t.s[k] = t.d[k] = r.pk[k] = r.f[k] = r.l[k] = 0;
+    r.b[k] = 0;
+  }
+  if (ok) {
+    t.v[0] = true;
+    t.s[0] = ldg_nt(a.src + idx);
+    t.d[0] = ldg_nt(a.dst + idx);
+    r.pk[0] = ldg_nt(a.packets + idx);
+    r.f[0] = ldg_nt(a.first + idx);
+    r.l[0] = ldg_nt(a.last + idx);
+    r.b[0] = ldg_nt(a.bytes + idx);
   }
 }
 
 struct Lds {
-  const uint32_t *root, *lmap, *lines;
+  const uint64_t *root;
+  const uint32_t *lines;
   u64 *acc;
 };
 
+// Classify the tile's records (addresses already loaded) and aggregate them.
+// The caller issues the loads of `r` just before, so their latency overlaps
+// the locality tests and the trie walk.
 template <int R, bool LINES_LDS, bool ACC_LDS>
-__device__ __forceinline__ void process_tile(const Tile<R> &t, const ClassifyArgs &a, const Lds &L,
-                                             u64 *g_tab) {
+__device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r, const ClassifyArgs &a,
+                                             const Lds &L, u64 *g_tab) {
   const uint32_t rows = a.rows;
-  uint32_t remote[R], site[R];
-  bool one[R], inbound[R];
+  // one root read per endpoint gives its locality and, for the remote one,
+  // the first trie entry of its walk
+  const uint32_t sh = 32u - a.root_bits, sb = 28u - a.root_bits;
+  uint32_t remote[R], re[R], site[R];
+  bool one[R], inbound[R], ls[R], ld[R], part = false;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const bool ls = is_local(L.lmap, a.local, t.s[k]);
-    const bool ld = is_local(L.lmap, a.local, t.d[k]);
-    one[k] = t.v[k] && ls != ld;
-    inbound[k] = ld;
-    remote[k] = ld ? t.s[k] : t.d[k];
+    const uint64_t es = L.root[t.s[k] >> sh], ed = L.root[t.d[k] >> sh];
+    const uint32_t ms = (uint32_t)(es >> 32) >> ((t.s[k] >> sb) & 15u);
+    const uint32_t md = (uint32_t)(ed >> 32) >> ((t.d[k] >> sb) & 15u);
+    ls[k] = ms & 1u;
+    ld[k] = md & 1u;
+    part |= ((ms | md) >> kLocalSubBlocks) & 1u;
+    re[k] = ld[k] ? (uint32_t)es : (uint32_t)ed;
   }
-  lookup_sites<R, LINES_LDS>(remote, one, site, L.root, a.wide, L.lines, a.lines, a.root_bits);
+  if (__builtin_amdgcn_ballot_w64(part)) {  // partly local sub-blocks: exact ranges
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint64_t es = L.root[t.s[k] >> sh], ed = L.root[t.d[k] >> sh];
+      if (((uint32_t)(es >> 32) >> (16u + ((t.s[k] >> sb) & 15u))) & 1u) ls[k] = in_ranges(a.local, t.s[k]);
+      if (((uint32_t)(ed >> 32) >> (16u + ((t.d[k] >> sb) & 15u))) & 1u) ld[k] = in_ranges(a.local, t.d[k]);
+      re[k] = ld[k] ? (uint32_t)es : (uint32_t)ed;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    one[k] = t.v[k] && ls[k] != ld[k];
+    inbound[k] = ld[k];
+    remote[k] = ld[k] ? t.s[k] : t.d[k];
+  }
+  lookup_sites<R, LINES_LDS>(remote, re, one, site, a.wide, L.lines, a.lines, a.root_bits);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     if (!t.v[k]) continue;
     const uint32_t row = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
-    const uint32_t dur = t.l[k] - t.f[k];
-    const bool bulk = t.b[k] > a.bulk_bytes && dur > 0u;
+    const uint32_t dur = r.l[k] - r.f[k];
+    const bool bulk = r.b[k] > a.bulk_bytes && dur > 0u;
     uint64_t rate = 0;
-    if (bulk) rate = rate_bps(t.b[k], dur);
-    accumulate<ACC_LDS>(L.acc, g_tab, rows, row, t.b[k], t.pk[k], dur, bulk, rate);
+    if (bulk) rate = rate_bps(r.b[k], dur);
+    accumulate<ACC_LDS>(L.acc, g_tab, row, r.b[k], r.pk[k], dur, bulk, rate);
+  }
+}
+
+// Records [lo, hi) of one window: tiles whose addresses are prefetched one
+// tile ahead; the other fields load when their tile is processed.
+template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS>
+__device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &L, u64 *g_tab, uint64_t lo,
+                                              uint64_t hi) {
+  constexpr uint64_t T = (uint64_t)kThreads * R;
+  Addr<R> cur;
+  load_addr<R, VEC>(cur, a, lo, hi);
+  for (uint64_t base = lo; base < hi; base += T) {
+    Rest<R> rest;
+    load_rest<R, VEC>(rest, a, base, hi);
+    Addr<R> nxt;
+    if (base + T < hi) load_addr<R, VEC>(nxt, a, base + T, hi);
+    process_tile<R, LINES_LDS, ACC_LDS>(cur, rest, a, L, g_tab);
+    cur = nxt;
   }
 }
 
@@ -400,23 +462,21 @@ __global__ void init_acc_kernel(u64 *__restrict__ acc, uint64_t words) {
 template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS>
 __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  uint32_t *s_root = (uint32_t *)lds;
-  uint32_t *s_lmap = (uint32_t *)(lds + a.lds_off_lmap);
+  uint64_t *s_root = (uint64_t *)lds;
   u64 *s_acc = (u64 *)(lds + a.lds_off_acc);
   uint32_t *s_lines = (uint32_t *)(lds + a.lds_off_lines);
   const uint32_t tid = threadIdx.x;
   const uint32_t rows = a.rows;
 
-  // stage the trie root, the locality map and (when they fit) the leaf lines
+  // stage the trie root (with locality masks) and, when they fit, the leaf lines
   const uint32_t nroot = 1u << a.root_bits;
   for (uint32_t i = tid; i < nroot; i += kThreads) s_root[i] = a.root[i];
-  for (uint32_t i = tid; i < kLocalMapWords; i += kThreads) s_lmap[i] = a.lmap[i];
   if (LINES_LDS)
     for (uint32_t i = tid; i < a.n_line_words; i += kThreads) s_lines[i] = a.lines[i];
   if (ACC_LDS)
-    for (uint32_t i = tid; i < kAccFields * rows; i += kThreads) s_acc[i] = (i / rows == kRateMin) ? ~0ull : 0ull;
+    for (uint32_t i = tid; i < kAccFields * rows; i += kThreads) s_acc[i] = (i % kAccFields == kRateMin) ? ~0ull : 0ull;
   __syncthreads();
-  const Lds L{s_root, s_lmap, s_lines, s_acc};
+  const Lds L{s_root, s_lines, s_acc};
 
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
@@ -439,39 +499,19 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
 
     if (VEC) {
       // whole groups of 4 records with vector loads; up to 3 records before
-      // and after them in one strided mini-tile
+      // and after them in one single-record mini-tile
       const uint64_t a0 = ((i + 3) & ~3ull) < seg_end ? ((i + 3) & ~3ull) : seg_end;
       const uint64_t a1 = a0 + ((seg_end - a0) & ~3ull);
       if (i < a0 || a1 < seg_end) {
-        Tile<R> m;
-        clear_tile(m);
-        if (tid < a0 - i) load_one(m, 0, a, i + tid);
-        else if (tid >= 3 && tid - 3 < seg_end - a1) load_one(m, 0, a, a1 + (tid - 3));
-        process_tile<R, LINES_LDS, ACC_LDS>(m, a, L, g_tab);
+        Addr<R> m;
+        Rest<R> mr;
+        const bool head = tid < a0 - i, tail = tid >= 3 && tid - 3 < seg_end - a1;
+        load_single(m, mr, a, head ? i + tid : a1 + (tid - 3), head || tail);
+        process_tile<R, LINES_LDS, ACC_LDS>(m, mr, a, L, g_tab);
       }
-      if (a0 < a1) {
-        constexpr uint64_t T = (uint64_t)kThreads * 4;
-        Tile<4> cur;
-        load_vec(cur, a, a0, a1);
-        for (uint64_t base = a0; base < a1; base += T) {
-          Tile<4> nxt;
-          if (base + T < a1) load_vec(nxt, a, base + T, a1);
-          else clear_tile(nxt);
-          process_tile<4, LINES_LDS, ACC_LDS>(cur, a, L, g_tab);
-          cur = nxt;
-        }
-      }
+      if (a0 < a1) process_range<4, true, LINES_LDS, ACC_LDS>(a, L, g_tab, a0, a1);
     } else {
-      constexpr uint64_t T = (uint64_t)kThreads * R;
-      Tile<R> cur;
-      load_strided(cur, a, i, seg_end);
-      for (uint64_t base = i; base < seg_end; base += T) {
-        Tile<R> nxt;
-        if (base + T < seg_end) load_strided(nxt, a, base + T, seg_end);
-        else clear_tile(nxt);
-        process_tile<R, LINES_LDS, ACC_LDS>(cur, a, L, g_tab);
-        cur = nxt;
-      }
+      process_range<R, false, LINES_LDS, ACC_LDS>(a, L, g_tab, i, seg_end);
     }
     if (ACC_LDS) {
       if (seg_end >= hi && a.ws) flush_partial(a, s_acc, w);
@@ -508,16 +548,17 @@ __global__ __launch_bounds__(kRedRows *kRedSubs) void reduce_partials_kernel(
   u64 v[8] = {0, 0, 0, 0, 0, 0, ~0ull, 0};
   if (r < rows) {
     const uint64_t words = (uint64_t)kAccFields * rows;
+#pragma unroll 4
     for (uint32_t b = b0 + sub; b < b1; b += kRedSubs) {
-      const u64 *p = ws + (uint64_t)b * words + r;
-      const u64 cnt = p[kCnt * rows];
+      const u64 *p = ws + (uint64_t)b * words + (uint64_t)r * kAccFields;
+      const u64 cnt = p[kCnt];
       v[0] += cnt & 0xFFFFFFFFull;
       v[4] += cnt >> 32;
-      v[1] += p[kBytes * rows];
-      v[2] += p[kPackets * rows];
-      v[3] += p[kDur * rows];
-      v[5] += p[kRateSum * rows];
-      const u64 mn = p[kRateMin * rows], mx = p[kRateMax * rows];
+      v[1] += p[kBytes];
+      v[2] += p[kPackets];
+      v[3] += p[kDur];
+      v[5] += p[kRateSum];
+      const u64 mn = p[kRateMin], mx = p[kRateMax];
       v[6] = mn < v[6] ? mn : v[6];
       v[7] = mx > v[7] ? mx : v[7];
     }
@@ -682,10 +723,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.first = rec->first_ms; a.last = rec->last_ms; a.n = rec->n;
   a.woff = (gu64 *)window_offsets; a.n_windows = n_windows; a.rows = (uint32_t)rows;
   a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
-  a.root = (gu32 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
-  a.lmap = (gu32 *)reg->d_lmap;
+  a.root = (gu64 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
   a.root_bits = reg->root_bits; a.n_line_words = (uint32_t)reg->lines.size();
-  a.lds_off_lmap = reg->lds_off_lmap; a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
+  a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
   if (use_ws) {
     a.ws = (u64 *)p.workspace;
     a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);

@@ -183,10 +183,12 @@ struct Layout {
       q[1] = k[3] | (kKindQuad << kKindShift);
       q[2] = st[0] | (st[1] << 16);
       q[3] = st[2] | (st[3] << 16);
-    } else if (count <= list_max) {
+    } else if (!quad_ok && count <= list_max) {
+      // 16-bit site codes do not fit: a leaf line (32-bit codes)
       q[1] = kKindLine << kKindShift;
       q[2] = add_line(lo, i0, count);
     } else {
+      // a deeper wide node, whose entries are again mostly leaves or quads
       const uint32_t child = wide_node(lo, shift);
       q[1] = kKindNode << kKindShift;
       q[2] = child;
@@ -240,45 +242,47 @@ bool host_in_ranges(const gnm_registry *r, uint32_t ip) {
   return false;
 }
 
-// Locality through the /16 map, as the device decides it.
+// Locality through the root cell's sub-block masks, as the device decides it.
 bool host_is_local(const gnm_registry *r, uint32_t ip) {
-  const uint32_t code = (r->lmap[ip >> 20] >> ((ip >> 15) & 30u)) & 3u;
-  return code == kLocalFull || (code == kLocalPart && host_in_ranges(r, ip));
+  const uint32_t m = r->root_local[ip >> (32u - r->root_bits)];
+  const uint32_t sub = (ip >> (28u - r->root_bits)) & 15u;
+  if ((m >> (16u + sub)) & 1u) return host_in_ranges(r, ip);
+  return (m >> sub) & 1u;
 }
 
-// 2 bits per /16 block: none, full or partial.  The ranges are disjoint and
-// coalesced, so a block is fully local only if one range covers all of it.
-void build_local_map(gnm_registry *r) {
-  r->lmap.assign(kLocalMapWords, 0u);
+// Per root cell, 16 sub-blocks of 2^(28 - root_bits) addresses each: bit j
+// if a local range covers sub-block j entirely, bit 16 + j if local ranges
+// cover part of it.  The ranges are disjoint and coalesced, so a sub-block is
+// entirely local only if one range covers it.
+void build_local_masks(gnm_registry *r) {
+  r->root_local.assign((size_t)1 << r->root_bits, 0u);
+  const uint32_t sb_shift = 28u - r->root_bits;
   for (size_t j = 0; j < r->local_lo.size(); ++j) {
-    const uint32_t lo = r->local_lo[j], hi = r->local_hi[j];
-    for (uint64_t b = lo >> 16; b <= (hi >> 16); ++b) {
-      const uint64_t blo = b << 16, bhi = blo | 0xFFFFu;
+    const uint64_t lo = r->local_lo[j], hi = r->local_hi[j];
+    for (uint64_t b = lo >> sb_shift; b <= (hi >> sb_shift); ++b) {
+      const uint64_t blo = b << sb_shift, bhi = blo + ((uint64_t)1 << sb_shift) - 1;
       const bool full = lo <= blo && hi >= bhi;
-      const uint32_t sh = (uint32_t)(b & 15u) * 2u;
-      uint32_t &w = r->lmap[b >> 4];
-      const uint32_t cur = (w >> sh) & 3u;
-      const uint32_t code = (full || cur == kLocalFull) ? kLocalFull : kLocalPart;
-      w = (w & ~(3u << sh)) | (code << sh);
+      uint32_t &m = r->root_local[b >> 4];
+      const uint32_t sub = (uint32_t)(b & 15u);
+      if (full) m = (m | (1u << sub)) & ~(1u << (16u + sub));
+      else if (!((m >> sub) & 1u)) m |= 1u << (16u + sub);
     }
   }
 }
 
-// LDS plan for a classify workgroup: root and local map, then (if it fits)
-// the accumulator table, then (if they fit) the leaf lines.
+// LDS plan for a classify workgroup: the root (with locality masks), then (if
+// it fits) the accumulator table, then (if they fit) the leaf lines.
 void plan_lds(gnm_registry *r, uint32_t lds_budget) {
-  const uint64_t root_b = 4ull << r->root_bits;
-  const uint64_t lmap_b = 4ull * kLocalMapWords;
+  const uint64_t root_b = 8ull << r->root_bits;
   const uint64_t line_b = 4ull * r->lines.size();
   const uint64_t acc_b = 8ull * kAccFields * r->rows();
-  uint64_t used = root_b + lmap_b;
+  uint64_t used = root_b;
   r->acc_in_lds = used + acc_b <= lds_budget;
   if (r->acc_in_lds) used += acc_b;
   used = (used + 15u) & ~15ull;  // 16-byte loads of line keys
   r->lines_in_lds = used + line_b <= lds_budget;
-  // layout: root | lmap | acc | lines   (all offsets multiples of 16 bytes)
-  r->lds_off_lmap = (uint32_t)root_b;
-  r->lds_off_acc = (uint32_t)(root_b + lmap_b);
+  // layout: root | acc | lines
+  r->lds_off_acc = (uint32_t)root_b;
   r->lds_off_lines = (uint32_t)used;
   r->lds_bytes = (uint32_t)(used + (r->lines_in_lds ? line_b : 0));
 }
@@ -301,10 +305,10 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   const uint32_t root_bits = o.root_bits ? o.root_bits : 12u;
   const uint32_t list_max = o.list_max ? o.list_max : kLineKeys;
   const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsMax;
-  if (root_bits < 8 || root_bits > 15) return fail(GNM_E_INVAL, "root_bits must be 8..15");
+  if (root_bits < 8 || root_bits > 14) return fail(GNM_E_INVAL, "root_bits must be 8..14");
   if (list_max < 2 || list_max > kLineKeys) return fail(GNM_E_INVAL, "list_max must be 2..8");
-  if (lds_budget > kLdsMax || lds_budget < (4u << root_bits) + 4u * kLocalMapWords)
-    return fail(GNM_E_INVAL, "lds_bytes cannot hold the root table and local map");
+  if (lds_budget > kLdsMax || lds_budget < (8u << root_bits))
+    return fail(GNM_E_INVAL, "lds_bytes cannot hold the root table");
 
   gnm_registry *r = new (std::nothrow) gnm_registry();
   if (!r) return fail(GNM_E_NOMEM, "host allocation failed");
@@ -366,11 +370,16 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
     // most lookups).
     const std::vector<Interval> iv = resolve(d, n_sites);
     r->info.n_intervals = iv.size();
-    build_local_map(r);
+    build_local_masks(r);
     const bool force_wide = (o.flags & GNM_REG_FORCE_WIDE) != 0;
     const bool force_lines = (o.flags & GNM_REG_FORCE_LINES) != 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
       Layout lay{&iv, list_max, !force_wide && attempt == 0, n_sites < 0xFFFFu, {}, {}};
+      // entry 0 of each array is a harmless dummy (a leaf of site 0) that lanes
+      // with nothing to look up may read instead of branching around the load
+      lay.wide.assign(4, 0u);
+      lay.wide[1] = kKindLeaf << kKindShift;
+      lay.lines.assign(kLineWords, 0u);
       r->root.assign((size_t)1 << root_bits, 0u);
       for (uint64_t b = 0; b < ((uint64_t)1 << root_bits); ++b) {
         const uint32_t e = lay.root_cell(b << (32 - root_bits), 32 - root_bits);
@@ -383,7 +392,7 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
       plan_lds(r, lds_budget);
       if (!lay.root_lines || force_lines || r->lines_in_lds) break;
     }
-    r->info.n_leaf_lines = r->lines.size() / kLineWords;
+    r->info.n_leaf_lines = r->lines.size() / kLineWords - 1;
   } catch (const std::bad_alloc &) {
     delete r;
     return fail(GNM_E_NOMEM, "host allocation failed");
@@ -402,12 +411,15 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
     return GNM_OK;
   }
 
-  // device upload: root | wide | lines | lmap, each 256-byte aligned
+  // device upload: root (64-bit: trie entry | locality masks << 32) | wide |
+  // lines, each 256-byte aligned
+  std::vector<uint64_t> root64(r->root.size());
+  for (size_t b = 0; b < root64.size(); ++b) root64[b] = (uint64_t)r->root[b] | ((uint64_t)r->root_local[b] << 32);
   auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
-  const uint64_t b_root = 4ull * r->root.size(), b_nodes = 4ull * r->wide.size();
-  const uint64_t b_lines = 4ull * r->lines.size(), b_lmap = 4ull * r->lmap.size();
-  const uint64_t o_nodes = al(b_root), o_lines = o_nodes + al(b_nodes), o_lmap = o_lines + al(b_lines);
-  const uint64_t total = o_lmap + al(b_lmap) + 256;
+  const uint64_t b_root = 8ull * root64.size(), b_nodes = 4ull * r->wide.size();
+  const uint64_t b_lines = 4ull * r->lines.size();
+  const uint64_t o_nodes = al(b_root), o_lines = o_nodes + al(b_nodes);
+  const uint64_t total = o_lines + al(b_lines) + 256;
   hipError_t e = hipGetDevice(&r->device);
   if (e == hipSuccess) e = hipMalloc(&r->d_buf, total);
   if (e != hipSuccess) {
@@ -416,14 +428,13 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
     return e == hipErrorOutOfMemory ? GNM_E_NOMEM : GNM_E_HIP;
   }
   char *base = (char *)r->d_buf;
-  r->d_root = (const uint32_t *)base;
+  r->d_root = (const uint64_t *)base;
   r->d_wide = (const uint32_t *)(base + o_nodes);
   r->d_lines = (const uint32_t *)(base + o_lines);
-  r->d_lmap = (const uint32_t *)(base + o_lmap);
   r->d_bytes = total;
   struct Part { const void *h; void *d; uint64_t b; } parts[] = {
-      {r->root.data(), (void *)r->d_root, b_root}, {r->wide.data(), (void *)r->d_wide, b_nodes},
-      {r->lines.data(), (void *)r->d_lines, b_lines}, {r->lmap.data(), (void *)r->d_lmap, b_lmap}};
+      {root64.data(), (void *)r->d_root, b_root}, {r->wide.data(), (void *)r->d_wide, b_nodes},
+      {r->lines.data(), (void *)r->d_lines, b_lines}};
   for (const Part &q : parts) {
     if (q.b == 0) continue;
     e = hipMemcpyAsync(q.d, q.h, q.b, hipMemcpyHostToDevice, stream);

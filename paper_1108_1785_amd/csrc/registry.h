@@ -16,9 +16,10 @@ struct gnm_registry {
 
   // host copy of the lookup structure (see gnm_internal.h)
   std::vector<uint32_t> root, wide, lines;
-  // local set as disjoint inclusive ranges [lo, hi], sorted, and its /16 map
+  // local set as disjoint inclusive ranges [lo, hi], sorted, and the
+  // locality masks of every root cell (high words of the device root entries)
   std::vector<uint32_t> local_lo, local_hi;
-  std::vector<uint32_t> lmap;
+  std::vector<uint32_t> root_local;
 
   gnm_registry_info info{};
 
@@ -26,13 +27,14 @@ struct gnm_registry {
   bool host_only = true;
   int device = -1;
   void *d_buf = nullptr;
-  const uint32_t *d_root = nullptr, *d_wide = nullptr, *d_lines = nullptr, *d_lmap = nullptr;
+  const uint64_t *d_root = nullptr;
+  const uint32_t *d_wide = nullptr, *d_lines = nullptr;
   uint64_t d_bytes = 0;
 
   // launch-time LDS plan
   bool lines_in_lds = false;
   bool acc_in_lds = false;
-  uint32_t lds_off_lmap = 0, lds_off_acc = 0, lds_off_lines = 0, lds_bytes = 0;
+  uint32_t lds_off_acc = 0, lds_off_lines = 0, lds_bytes = 0;
 
   uint64_t rows() const { return 2ull * (n_sites + 1ull) + 1ull; }
 };

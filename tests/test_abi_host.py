@@ -68,7 +68,7 @@ def test_worked_example_host_lookup():
 
 
 @pytest.mark.parametrize("layout", ["lines", "wide"])
-@pytest.mark.parametrize("root_bits,list_max", [(8, 2), (8, 8), (12, 4), (15, 2), (15, 8), (10, 3)])
+@pytest.mark.parametrize("root_bits,list_max", [(8, 2), (8, 8), (12, 4), (14, 2), (14, 8), (10, 3)])
 @pytest.mark.parametrize("seed", range(12))
 def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max, layout):
     rng = np.random.default_rng(1000 + seed)
@@ -124,7 +124,7 @@ def test_registry_errors(sites, n_sites, local, code):
 
 
 def test_build_option_errors():
-    for kw in (dict(root_bits=7), dict(root_bits=16), dict(list_max=1), dict(list_max=9)):
+    for kw in (dict(root_bits=7), dict(root_bits=15), dict(list_max=1), dict(list_max=9)):
         with pytest.raises(gnm.GnmError) as e:
             _host_reg([], [], 1, **kw)
         assert e.value.code == gnm.GNM_E_INVAL

@@ -119,9 +119,9 @@ def test_workspace_too_small_falls_back(torch_cuda):
 
 
 @pytest.mark.parametrize("kw", [dict(layout="wide"), dict(layout="wide", root_bits=8), dict(layout="lines"),
-                                dict(root_bits=8, list_max=2), dict(root_bits=15, list_max=8),
-                                dict(root_bits=10, list_max=3), dict(lds_bytes=4096 + 16384 + 256, root_bits=10),
-                                dict(lds_bytes=1024 + 16384, root_bits=8)])
+                                dict(root_bits=8, list_max=2), dict(root_bits=14, list_max=8),
+                                dict(root_bits=10, list_max=3), dict(lds_bytes=8192 + 256, root_bits=10),
+                                dict(lds_bytes=2048, root_bits=8)])
 def test_registry_layout_variants(torch_cuda, kw):
     say("case: layout", kw)
     s = _small()
@@ -154,7 +154,7 @@ def test_edge_registries_and_records(torch_cuda):
                                                      n_local=int(rng.integers(0, 4)))
         recs = _edge_records(rng, int(rng.integers(0, 3000)), sites, local)
         bulk = int(rng.choice([0, 1_000_000, 1 << 40]))
-        kw = dict(root_bits=int(rng.integers(8, 16)), list_max=int(rng.integers(2, 9)),
+        kw = dict(root_bits=int(rng.integers(8, 15)), list_max=int(rng.integers(2, 9)),
                   layout=str(rng.choice(["auto", "wide", "lines"])))
         reg, orc = _regs(sites, local, n_sites, **kw)
         rec = soa(recs)
