@@ -256,6 +256,61 @@ int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_
                         uint64_t threshold_bps, uint64_t min_bulk_flows, uint8_t *flags,
                         hipStream_t stream);
 
+/* ------------------------------------------------------------------ batched form
+ * Many windows of uneven size go through one persistent classify launch (see
+ * gnm_classify_aggregate with window offsets); the paper instead launches once
+ * per hourly window (§III.B.1, NetPerf Monitoring Thread).  For a step that
+ * repeats over the same buffers, the launch sequence can be captured once into
+ * a HIP graph and replayed.
+ */
+typedef struct gnm_graph gnm_graph; /* opaque */
+
+/*
+ * gnm_graph_create — capture one step: gnm_classify_aggregate(reg, rec,
+ * window_offsets, n_windows, p, acc) followed, when flags is not NULL, by
+ * gnm_flag_suboptimal(reg, acc, n_windows, threshold_bps, min_bulk_flows,
+ * flags).  All pointers (records, offsets, acc, flags, p->workspace) are
+ * baked into the graph: every replay reads and writes those same buffers,
+ * whose contents the caller may change between replays.  The call runs the
+ * step once eagerly (results valid on return) and synchronises its own
+ * private stream.  Errors: those of the two captured calls, GNM_E_HIP.
+ */
+int gnm_graph_create(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                     uint32_t n_windows, const gnm_params *p, gnm_acc *acc, uint64_t threshold_bps,
+                     uint64_t min_bulk_flows, uint8_t *flags, gnm_graph **out);
+
+/* Replay a captured step on `stream`.  Replays on one graph must not overlap
+ * (they share buffers). */
+int gnm_graph_launch(gnm_graph *g, hipStream_t stream);
+
+/* Free a graph (NULL is a no-op); its replays must have completed. */
+int gnm_graph_free(gnm_graph *g);
+
+#define GNM_TUNE_MAX 16
+/* Result of gnm_autotune: the fastest parameters and every timing taken. */
+typedef struct {
+  gnm_params best;                         /* base parameters with the best launch shape */
+  float best_ms;                           /* median classify-call time of `best` */
+  uint32_t n_tried;
+  float ms[GNM_TUNE_MAX];                  /* median time of candidate i */
+  uint32_t records_per_thread[GNM_TUNE_MAX];
+  uint32_t grid_blocks[GNM_TUNE_MAX];      /* 0 = automatic */
+} gnm_tune_result;
+
+/*
+ * gnm_autotune — time gnm_classify_aggregate on the caller's own records for
+ * candidate launch shapes (records per lane 4, 2, 1 x automatic, half, double
+ * and quadruple workgroup counts), each as a warm-up plus the median of `reps`
+ * (0 = 3) timed calls on `stream`, and return the fastest.  acc is
+ * overwritten (initialised per call unless base->flags has GNM_ACCUMULATE,
+ * in which case it accumulates every timed call).  Candidates whose
+ * workgroup count needs more workspace than base->workspace_bytes merge with
+ * atomics.  Synchronous.  Errors: those of gnm_classify_aggregate, GNM_E_HIP.
+ */
+int gnm_autotune(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                 uint32_t n_windows, const gnm_params *base, gnm_acc *acc, uint32_t reps,
+                 hipStream_t stream, gnm_tune_result *out);
+
 /* Static description of an error code. */
 const char *gnm_strerror(int code);
 

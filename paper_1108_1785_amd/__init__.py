@@ -36,7 +36,9 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
            "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_classify_aggregate",
-           "gnm_flag_suboptimal", "gnm_strerror", "gnm_last_error", "gnm_version")
+           "gnm_flag_suboptimal", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
+           "gnm_strerror", "gnm_last_error", "gnm_version")
+TUNE_MAX = 16
 
 
 class Prefix(ctypes.Structure):
@@ -55,6 +57,12 @@ class Params(ctypes.Structure):
                 ("records_per_thread", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_uint64)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", Params), ("best_ms", ctypes.c_float), ("n_tried", ctypes.c_uint32),
+                ("ms", ctypes.c_float * TUNE_MAX), ("records_per_thread", ctypes.c_uint32 * TUNE_MAX),
+                ("grid_blocks", ctypes.c_uint32 * TUNE_MAX)]
 
 
 class RegistryOpts(ctypes.Structure):
@@ -117,6 +125,16 @@ def lib():
         L.gnm_classify_aggregate.restype = ctypes.c_int
         L.gnm_flag_suboptimal.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.gnm_flag_suboptimal.restype = ctypes.c_int
+        L.gnm_graph_create.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32, ctypes.POINTER(Params), P,
+                                       ctypes.c_uint64, ctypes.c_uint64, P, ctypes.POINTER(P)]
+        L.gnm_graph_create.restype = ctypes.c_int
+        L.gnm_graph_launch.argtypes = [P, P]
+        L.gnm_graph_launch.restype = ctypes.c_int
+        L.gnm_graph_free.argtypes = [P]
+        L.gnm_graph_free.restype = ctypes.c_int
+        L.gnm_autotune.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32, ctypes.POINTER(Params), P,
+                                   ctypes.c_uint32, P, ctypes.POINTER(TuneResult)]
+        L.gnm_autotune.restype = ctypes.c_int
         L.gnm_strerror.argtypes = [ctypes.c_int]
         L.gnm_strerror.restype = ctypes.c_char_p
         L.gnm_last_error.argtypes = []
@@ -289,6 +307,60 @@ def flag_suboptimal(reg: Registry, acc, n_windows: int, flags, threshold_bps: in
     _check(lib().gnm_flag_suboptimal(reg.handle, ctypes.c_void_p(acc.data_ptr()), int(n_windows),
                                      int(threshold_bps), int(min_bulk_flows), ctypes.c_void_p(flags.data_ptr()),
                                      _stream_handle(stream)), "gnm_flag_suboptimal")
+
+
+class Graph:
+    """gnm_graph_create / gnm_graph_launch / gnm_graph_free: one captured step.
+
+    Holds references to every tensor baked into the graph so they outlive it.
+    """
+
+    def __init__(self, reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1, flags=None,
+                 threshold_bps: int = 1_000_000, min_bulk_flows: int = 0, n: Optional[int] = None, **params):
+        self._keep = (reg, rec, acc, window_offsets, flags, params.get("workspace"))
+        self._rec = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
+        self._p = make_params(**params)
+        off = 0 if window_offsets is None else window_offsets.data_ptr()
+        fl = 0 if flags is None else flags.data_ptr()
+        h = ctypes.c_void_p()
+        _check(lib().gnm_graph_create(reg.handle, ctypes.byref(self._rec), ctypes.c_void_p(off), int(n_windows),
+                                      ctypes.byref(self._p), ctypes.c_void_p(acc.data_ptr()), int(threshold_bps),
+                                      int(min_bulk_flows), ctypes.c_void_p(fl), ctypes.byref(h)),
+               "gnm_graph_create")
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().gnm_graph_launch(self._h, _stream_handle(stream)), "gnm_graph_launch")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().gnm_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1, reps: int = 3,
+             stream=None, n: Optional[int] = None, **params) -> Dict[str, object]:
+    """gnm_autotune: fastest launch shape for this registry and these records.
+
+    Returns {"records_per_thread", "grid_blocks", "best_ms", "tried": [(rpt, grid, ms), ...]}.
+    """
+    c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
+    p = make_params(**params)
+    off = 0 if window_offsets is None else window_offsets.data_ptr()
+    out = TuneResult()
+    _check(lib().gnm_autotune(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows), ctypes.byref(p),
+                              ctypes.c_void_p(acc.data_ptr()), int(reps), _stream_handle(stream),
+                              ctypes.byref(out)), "gnm_autotune")
+    tried = [(int(out.records_per_thread[i]), int(out.grid_blocks[i]), float(out.ms[i]))
+             for i in range(out.n_tried)]
+    return {"records_per_thread": int(out.best.records_per_thread), "grid_blocks": int(out.best.grid_blocks),
+            "best_ms": float(out.best_ms), "tried": tried}
 
 
 def version() -> str:

@@ -1,0 +1,80 @@
+"""Autotuning cache for the batched form.
+
+gnm_autotune (C ABI) times launch shapes on the caller's own records; this
+module remembers the winner in a JSON file keyed by device, library version,
+registry shape and workload size, so later runs of the same workload skip the
+search.  The cache holds launch parameters only, never results.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, Optional
+
+from . import Registry, autotune, lib, version
+
+DEFAULT_CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "gnm", "tune.json")
+
+
+def _cache_path() -> str:
+    return os.environ.get("GNM_TUNE_CACHE", DEFAULT_CACHE)
+
+
+def _device_name() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return "%s/%s/%d" % (p.name, getattr(p, "gcnArchName", ""), p.multi_processor_count)
+
+
+def workload_key(reg: Registry, n_records: int, n_windows: int) -> str:
+    i = reg.info()
+    shape = "p%d-s%d-r%d-l%d-li%d-ai%d" % (i["n_prefixes"], i["n_sites"], i["root_bits"], i["list_max"],
+                                          i["lines_in_lds"], i["acc_in_lds"])
+    # sizes bucketed by powers of two: the best shape changes slowly with size
+    nb = int(math.log2(max(n_records, 1)))
+    wb = int(math.log2(max(n_windows, 1)))
+    return "%s|%s|%s|n2^%d|w2^%d" % (_device_name(), version(), shape, nb, wb)
+
+
+def _load(path: str) -> Dict[str, dict]:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, data: Dict[str, dict]) -> None:
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only cache only costs a re-tune
+
+
+def tuned_params(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1, n: Optional[int] = None,
+                 workspace=None, reps: int = 3, refresh: bool = False,
+                 cache_path: Optional[str] = None) -> Dict[str, object]:
+    """{"records_per_thread", "grid_blocks", ...} for this workload, tuned once and cached."""
+    lib()
+    path = cache_path or _cache_path()
+    n_rec = int(n if n is not None else rec["src_ip"].numel())
+    key = workload_key(reg, n_rec, n_windows)
+    data = _load(path)
+    if not refresh and key in data:
+        hit = dict(data[key])
+        hit["cached"] = True
+        return hit
+    res = autotune(reg, rec, acc, window_offsets=window_offsets, n_windows=n_windows, reps=reps, n=n_rec,
+                   workspace=workspace)
+    entry = {"records_per_thread": res["records_per_thread"], "grid_blocks": res["grid_blocks"],
+             "best_ms": res["best_ms"], "tried": res["tried"]}
+    data[key] = entry
+    _store(path, data)
+    out = dict(entry)
+    out["cached"] = False
+    return out

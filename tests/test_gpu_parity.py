@@ -323,3 +323,65 @@ def test_plain_large_full_size(torch_cuda):
         got = run(reg, rec, dev_rec=d, workspace=ws)
         assert (got == exp).all(), diff(got, exp)
     assert (flags(reg, got) == oracle.flags(exp, r.n_sites)).all()
+
+
+def test_graph_replays_match_oracle(torch_cuda):
+    import torch
+    say("case: hipGraph replay of a batched step, buffers refilled between replays")
+    r = flowgen.registry_for(flowgen.PLAIN_SMALL)
+    orc = oracle.Registry.from_generated(r)
+    reg = gnm.Registry.from_generated(r)
+    recs = [flowgen.records_for(flowgen.BATCHED, reg=r, n=1_500_000) for _ in range(1)]
+    rec_a = recs[0]
+    # a second batch with the same window sizes but other records
+    rng = np.random.default_rng(5)
+    rec_b = flowgen.permuted(rec_a, rng)
+    rec_b.window_offsets = rec_a.window_offsets
+    nw = rec_a.n_windows
+    d = to_device(rec_a)
+    off = torch.from_numpy(rec_a.window_offsets.view(np.int64)).to("cuda:0")
+    acc = torch.empty((nw, reg.rows, 8), dtype=torch.int64, device="cuda:0")
+    flg = torch.empty(nw * r.n_sites, dtype=torch.uint8, device="cuda:0")
+    ws = gnm.make_workspace(reg)
+    g = gnm.Graph(reg, d, acc, window_offsets=off, n_windows=nw, flags=flg, n=rec_a.n, workspace=ws)
+    exp_a = orc.classify_aggregate(rec_a)
+    exp_b = orc.classify_aggregate(rec_b)
+    db = to_device(rec_b)
+    for it in range(4):
+        use_b = it % 2 == 1
+        src = db if use_b else to_device(rec_a)
+        for f in d:
+            d[f].copy_(src[f])  # refill the captured buffers (eager work between replays)
+        acc.fill_(7)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        exp = exp_b if use_b else exp_a
+        got = gnm.acc_to_numpy(acc)
+        assert (got == exp).all(), (it, diff(got, exp))
+        assert (flg.cpu().numpy().reshape(nw, r.n_sites) == oracle.flags(exp, r.n_sites)).all()
+    g.close()
+
+
+def test_autotune_choice_is_exact(torch_cuda, tmp_path):
+    import torch
+    from paper_1108_1785_amd import tune
+    say("case: autotune then run with the tuned shape")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = flowgen.records_for(flowgen.BATCHED, reg=s["reg"], n=2_000_000)
+    d = to_device(rec)
+    off = torch.from_numpy(rec.window_offsets.view(np.int64)).to("cuda:0")
+    nw = rec.n_windows
+    acc = torch.empty((nw, reg.rows, 8), dtype=torch.int64, device="cuda:0")
+    ws = gnm.make_workspace(reg)
+    cache = str(tmp_path / "tune.json")
+    t = tune.tuned_params(reg, d, acc, window_offsets=off, n_windows=nw, n=rec.n, workspace=ws, cache_path=cache)
+    say("  tuned", t)
+    assert not t["cached"] and t["records_per_thread"] in (1, 2, 4) and len(t["tried"]) >= 6
+    t2 = tune.tuned_params(reg, d, acc, window_offsets=off, n_windows=nw, n=rec.n, workspace=ws, cache_path=cache)
+    assert t2["cached"] and t2["records_per_thread"] == t["records_per_thread"]
+    exp = oracle.Registry.from_generated(s["reg"]).classify_aggregate(rec)
+    got = run(reg, rec, records_per_thread=t["records_per_thread"], grid_blocks=t["grid_blocks"],
+              workspace=gnm.make_workspace(reg, t["grid_blocks"]))
+    assert (got == exp).all(), diff(got, exp)
