@@ -128,7 +128,9 @@ typedef struct {
   uint32_t flags;          /* GNM_REG_HOST_ONLY: no device upload (inspection only) */
   uint32_t root_bits;      /* 0 = automatic (12); else 8..14 bits indexed by the LDS-resident top level */
   uint32_t list_max;       /* 0 = automatic (8); else 2..8 intervals per 64-byte leaf line */
-  uint32_t lds_bytes;      /* 0 = automatic; LDS budget of the lookup structure */
+  uint32_t lds_bytes;      /* 0 = automatic (147456); else the LDS budget, at most 147456 bytes, of the
+                              root table, accumulator table and leaf lines: what does not fit stays in
+                              device memory.  A classify workgroup also uses 16 KiB of LDS for staging. */
 } gnm_registry_opts;
 
 /* Facts about a built registry. */

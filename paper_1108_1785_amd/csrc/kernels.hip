@@ -17,11 +17,14 @@
 //     whose 16-byte entries usually hold a whole cell, so one cached read
 //     resolves a lookup; the R lookups of a lane advance in lockstep so their
 //     memory accesses overlap;
-//   * a per-workgroup accumulator table in LDS (structure of arrays of u64,
+//   * a per-workgroup accumulator table in LDS (rows of seven u64 words,
 //     ds_add/ds_min/ds_max_u64);
 //   * an exact integer rate: a correctly rounded f64 quotient, within one of
 //     the answer for 8000*bytes < 2^53, corrected by one integer
-//     multiply-compare; a 64-bit long division covers larger byte counts;
+//     multiply-compare; a 64-bit long division covers larger byte counts.
+//     Each wave first compacts its bulk records (about one in six) through
+//     LDS, so the division runs once per 64 bulk records, not once per
+//     record slot;
 //   * each workgroup's final table written with plain coalesced stores to a
 //     caller workspace and combined by a small reduce kernel (device-scope
 //     atomics, which serialise across the chip, are used only for tables
@@ -46,8 +49,9 @@ typedef __attribute__((address_space(1))) const uint32_t gu32;
 typedef __attribute__((address_space(1))) const uint64_t gu64;
 
 constexpr uint32_t kThreads = 1024;
-constexpr uint32_t kRedRows = 8;   // reduce kernel: rows per workgroup
-constexpr uint32_t kRedSubs = 32;  // reduce kernel: partial tables summed in parallel per row
+static_assert(kStageBytes == (kThreads / 64u) * kStageEntries * 16u, "one staging area per wave");
+constexpr uint32_t kRedWords = 64;   // reduce kernel: table words per workgroup
+constexpr uint32_t kRedGroups = 16;  // reduce kernel: waves, each summing every 16th slot
 
 struct LocalRanges {
   uint32_t n;
@@ -69,7 +73,7 @@ struct ClassifyArgs {
   gu32 *wide, *lines;
   uint32_t root_bits;
   uint32_t n_line_words;
-  uint32_t lds_off_acc, lds_off_lines;
+  uint32_t lds_off_stage, lds_off_acc, lds_off_lines;
   u64 *ws;             // NULL: every table is flushed with atomics
   uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
   LocalRanges local;
@@ -219,27 +223,42 @@ __device__ __forceinline__ uint32_t window_of(const ClassifyArgs &a, uint64_t i,
 
 // ---------------------------------------------------------------- accumulation
 
+// Fields every record updates (the bulk count rides in the packed `cnt`).
 template <bool ACC_LDS>
 __device__ __forceinline__ void accumulate(u64 *s_acc, u64 *g_row, uint32_t row, uint64_t b, uint32_t pk,
-                                           uint32_t dur, bool bulk, uint64_t rate) {
+                                           uint32_t dur, bool bulk) {
   if (ACC_LDS) {
     u64 *t = s_acc + row * kAccFields;  // one address, immediate field offsets
     atomicAdd(&t[kCnt], 1ull | ((u64)bulk << 32));
     atomicAdd(&t[kBytes], (u64)b);
     atomicAdd(&t[kPackets], (u64)pk);
     atomicAdd(&t[kDur], (u64)dur);
-    if (bulk) {
-      atomicAdd(&t[kRateSum], (u64)rate);
-      atomicMin(&t[kRateMin], (u64)rate);
-      atomicMax(&t[kRateMax], (u64)rate);
-    }
   } else {
     u64 *g = g_row + (uint64_t)row * 8u;
     atomicAdd(&g[0], 1ull);
     atomicAdd(&g[1], (u64)b);
     atomicAdd(&g[2], (u64)pk);
     atomicAdd(&g[3], (u64)dur);
-    if (bulk) {
+  }
+}
+
+// Rates of the bulk records a wave has staged (entry: bytes lo, bytes hi,
+// duration, row), one per lane, and their rate fields.  Only about one record
+// in six is bulk, so the wave computes the division once for up to 64 staged
+// records instead of once per record slot of every lane.
+template <bool ACC_LDS>
+__device__ __forceinline__ void drain_bulk(const u32x4 *stage, uint32_t count, u64 *s_acc, u64 *g_row) {
+  const uint32_t lane = threadIdx.x & 63u;
+  if (lane < count) {
+    const u32x4 e = stage[lane];
+    const uint64_t rate = rate_bps((uint64_t)e.x | ((uint64_t)e.y << 32), e.z);
+    if (ACC_LDS) {
+      u64 *t = s_acc + e.w * kAccFields;
+      atomicAdd(&t[kRateSum], (u64)rate);
+      atomicMin(&t[kRateMin], (u64)rate);
+      atomicMax(&t[kRateMax], (u64)rate);
+    } else {
+      u64 *g = g_row + (uint64_t)e.w * 8u;
       atomicAdd(&g[4], 1ull);
       atomicAdd(&g[5], (u64)rate);
       atomicMin(&g[6], (u64)rate);
@@ -382,6 +401,7 @@ struct Lds {
   const uint64_t *root;
   const uint32_t *lines;
   u64 *acc;
+  u32x4 *stage;  // this wave's kStageEntries staging entries
 };
 
 // Classify the tile's records (addresses already loaded) and aggregate them.
@@ -422,16 +442,29 @@ __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r,
     remote[k] = ld[k] ? t.s[k] : t.d[k];
   }
   lookup_sites<R, LINES_LDS>(remote, re, one, site, a.wide, L.lines, a.lines, a.root_bits);
+  // Per-record fields now; bulk records are compacted into the wave's
+  // staging area (in LDS, written and read by this wave only, in order) and
+  // their rates computed together.
+  uint32_t fill = 0;  // wave-uniform
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    if (!t.v[k]) continue;
     const uint32_t row = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
     const uint32_t dur = r.l[k] - r.f[k];
-    const bool bulk = r.b[k] > a.bulk_bytes && dur > 0u;
-    uint64_t rate = 0;
-    if (bulk) rate = rate_bps(r.b[k], dur);
-    accumulate<ACC_LDS>(L.acc, g_tab, row, r.b[k], r.pk[k], dur, bulk, rate);
+    const bool bulk = t.v[k] && r.b[k] > a.bulk_bytes && dur > 0u;
+    if (t.v[k]) accumulate<ACC_LDS>(L.acc, g_tab, row, r.b[k], r.pk[k], dur, bulk);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(bulk);
+    const uint32_t c = (uint32_t)__builtin_popcountll(m);
+    if (fill + c > kStageEntries) {
+      drain_bulk<ACC_LDS>(L.stage, fill, L.acc, g_tab);
+      fill = 0;
+    }
+    if (bulk) {
+      const uint32_t pos = fill + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      L.stage[pos] = u32x4{(uint32_t)r.b[k], (uint32_t)(r.b[k] >> 32), dur, row};
+    }
+    fill += c;
   }
+  if (fill) drain_bulk<ACC_LDS>(L.stage, fill, L.acc, g_tab);
 }
 
 // Records [lo, hi) of one window: tiles whose addresses are prefetched one
@@ -476,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   if (ACC_LDS)
     for (uint32_t i = tid; i < kAccFields * rows; i += kThreads) s_acc[i] = (i % kAccFields == kRateMin) ? ~0ull : 0ull;
   __syncthreads();
-  const Lds L{s_root, s_lines, s_acc};
+  const Lds L{s_root, s_lines, s_acc, (u32x4 *)(lds + a.lds_off_stage) + (tid >> 6) * kStageEntries};
 
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
@@ -521,14 +554,17 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   }
 }
 
-// Combine the workgroups' final tables: workgroup w * row_tiles + x owns
-// kRedRows rows (tile x) of window w and sums, with kRedSubs lanes per row, the slots whose window is w
-// (a contiguous range, since slot windows never decrease).  Adds into acc, or
+// Combine the workgroups' final tables.  The slots whose window is w form a
+// contiguous range (slot windows never decrease).  Workgroup
+// w * word_tiles + x owns 64 consecutive words (tile x) of window w's
+// flattened table (rows of kAccFields words): lane j of each of its 16 waves
+// reads word j of every 16th slot, so each wave load is one contiguous
+// 512-byte run, and the waves' partial results meet in LDS.  Adds into acc, or
 // overwrites it when the classify launch left no other contribution.
-__global__ __launch_bounds__(kRedRows *kRedSubs) void reduce_partials_kernel(
+__global__ __launch_bounds__(kRedWords *kRedGroups) void reduce_partials_kernel(
     const u64 *__restrict__ ws, const uint32_t *__restrict__ meta, uint32_t slots, uint32_t rows,
-    u64 *__restrict__ acc, uint32_t row_tiles, uint32_t overwrite) {
-  const uint32_t w = blockIdx.x / row_tiles, tile = blockIdx.x - w * row_tiles;
+    u64 *__restrict__ acc, uint32_t word_tiles, uint32_t overwrite) {
+  const uint32_t w = blockIdx.x / word_tiles, tile = blockIdx.x - w * word_tiles;
   uint32_t b0 = 0, len = slots;  // first slot with meta >= w
   while (len > 0) {
     const uint32_t half = len >> 1;
@@ -543,43 +579,51 @@ __global__ __launch_bounds__(kRedRows *kRedSubs) void reduce_partials_kernel(
     else len = half;
   }
   if (b0 == b1) return;
-  const uint32_t r = tile * kRedRows + (threadIdx.x % kRedRows);
-  const uint32_t sub = threadIdx.x / kRedRows;
-  u64 v[8] = {0, 0, 0, 0, 0, 0, ~0ull, 0};
-  if (r < rows) {
-    const uint64_t words = (uint64_t)kAccFields * rows;
+  const uint32_t lane = threadIdx.x % kRedWords, g = threadIdx.x / kRedWords;
+  const uint32_t words = kAccFields * rows;
+  const uint32_t i = tile * kRedWords + lane;
+  const uint32_t f = i % kAccFields;
+  // x: sum (or min / max) of the word; y: bulk flows, for the packed count word
+  u64 x = f == kRateMin ? ~0ull : 0ull, y = 0;
+  if (i < words) {
+    const u64 *p = ws + (uint64_t)(b0 + g) * words + i;
+    const uint64_t step = (uint64_t)kRedGroups * words;
 #pragma unroll 4
-    for (uint32_t b = b0 + sub; b < b1; b += kRedSubs) {
-      const u64 *p = ws + (uint64_t)b * words + (uint64_t)r * kAccFields;
-      const u64 cnt = p[kCnt];
-      v[0] += cnt & 0xFFFFFFFFull;
-      v[4] += cnt >> 32;
-      v[1] += p[kBytes];
-      v[2] += p[kPackets];
-      v[3] += p[kDur];
-      v[5] += p[kRateSum];
-      const u64 mn = p[kRateMin], mx = p[kRateMax];
-      v[6] = mn < v[6] ? mn : v[6];
-      v[7] = mx > v[7] ? mx : v[7];
+    for (uint32_t b = b0 + g; b < b1; b += kRedGroups, p += step) {
+      const u64 v = __builtin_nontemporal_load(p);
+      if (f == kCnt) { x += v & 0xFFFFFFFFull; y += v >> 32; }
+      else if (f == kRateMin) x = v < x ? v : x;
+      else if (f == kRateMax) x = v > x ? v : x;
+      else x += v;
     }
   }
-  __shared__ u64 red[kRedSubs][8][kRedRows];
-  for (int f = 0; f < 8; ++f) red[sub][f][threadIdx.x % kRedRows] = v[f];
+  __shared__ u64 red[kRedGroups][2][kRedWords];
+  red[g][0][lane] = x;
+  red[g][1][lane] = y;
   __syncthreads();
-  if (sub != 0 || r >= rows) return;
-  for (uint32_t s = 1; s < kRedSubs; ++s) {
-    for (int f = 0; f < 6; ++f) v[f] += red[s][f][threadIdx.x];
-    const u64 mn = red[s][6][threadIdx.x], mx = red[s][7][threadIdx.x];
-    v[6] = mn < v[6] ? mn : v[6];
-    v[7] = mx > v[7] ? mx : v[7];
+  if (g != 0 || i >= words) return;
+  for (uint32_t s = 1; s < kRedGroups; ++s) {
+    const u64 v = red[s][0][lane];
+    if (f == kRateMin) x = v < x ? v : x;
+    else if (f == kRateMax) x = v > x ? v : x;
+    else x += v;
+    y += red[s][1][lane];
   }
+  // table word (row, f) -> acc fields: cnt -> flows (0) and bulk flows (4);
+  // bytes, packets, duration -> 1..3; rate sum, min, max -> 5..7
+  const uint32_t r = i / kAccFields;
   u64 *o = acc + ((uint64_t)w * rows + r) * 8u;
+  const uint32_t of = f == kCnt ? 0u : (f < kRateSum ? f : f + 1u);
   if (overwrite) {
-    for (int f = 0; f < 8; ++f) o[f] = v[f];
+    o[of] = x;
+    if (f == kCnt) o[4] = y;
+  } else if (f == kRateMin) {
+    o[of] = x < o[of] ? x : o[of];
+  } else if (f == kRateMax) {
+    o[of] = x > o[of] ? x : o[of];
   } else {
-    for (int f = 0; f < 6; ++f) o[f] += v[f];
-    o[6] = v[6] < o[6] ? v[6] : o[6];
-    o[7] = v[7] > o[7] ? v[7] : o[7];
+    o[of] += x;
+    if (f == kCnt) o[4] += y;
   }
 }
 
@@ -701,8 +745,14 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   uint64_t grid = p.grid_blocks ? p.grid_blocks : (tiles < resident ? tiles : resident);
   if (grid == 0) grid = 1;
   if (grid > 65535u * 16u) grid = 65535u * 16u;
+  if ((uint64_t)n_windows * rows * 8u > (uint64_t)INT32_MAX * 256u) {
+    set_last_error("accumulator tables too large");
+    return GNM_E_INVAL;
+  }
+  const uint64_t word_tiles = (kAccFields * rows + kRedWords - 1) / kRedWords;
   const bool use_ws = rec->n > 0 && reg->acc_in_lds && p.workspace &&
-                      p.workspace_bytes >= partial_bytes(reg, grid) && aligned16(p.workspace);
+                      p.workspace_bytes >= partial_bytes(reg, grid) && aligned16(p.workspace) &&
+                      word_tiles * n_windows <= (uint64_t)INT32_MAX;
   // With one window, a workspace, no accumulation and slices short enough to
   // need no mid-launch flush, the reduce kernel writes every row of the
   // table, so it needs no initialisation.
@@ -725,7 +775,7 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
   a.root = (gu64 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
   a.root_bits = reg->root_bits; a.n_line_words = (uint32_t)reg->lines.size();
-  a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
+  a.lds_off_stage = reg->lds_off_stage; a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
   if (use_ws) {
     a.ws = (u64 *)p.workspace;
     a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);
@@ -746,10 +796,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
   if (use_ws) {
-    const uint32_t row_tiles = (uint32_t)((rows + kRedRows - 1) / kRedRows);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)((uint64_t)row_tiles * n_windows)),
-                       dim3(kRedRows * kRedSubs), 0, stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta,
-                       (uint32_t)grid, (uint32_t)rows, (u64 *)acc, row_tiles, overwrite ? 1u : 0u);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(word_tiles * n_windows)),
+                       dim3(kRedWords * kRedGroups), 0, stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta,
+                       (uint32_t)grid, (uint32_t)rows, (u64 *)acc, (uint32_t)word_tiles, overwrite ? 1u : 0u);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
   }

@@ -273,6 +273,8 @@ void build_local_masks(gnm_registry *r) {
 // LDS plan for a classify workgroup: the root (with locality masks), then (if
 // it fits) the accumulator table, then (if they fit) the leaf lines.
 void plan_lds(gnm_registry *r, uint32_t lds_budget) {
+  // The budget covers root, accumulator table and leaf lines; the bulk-record
+  // staging area comes on top of it.
   const uint64_t root_b = 8ull << r->root_bits;
   const uint64_t line_b = 4ull * r->lines.size();
   const uint64_t acc_b = 8ull * kAccFields * r->rows();
@@ -281,10 +283,11 @@ void plan_lds(gnm_registry *r, uint32_t lds_budget) {
   if (r->acc_in_lds) used += acc_b;
   used = (used + 15u) & ~15ull;  // 16-byte loads of line keys
   r->lines_in_lds = used + line_b <= lds_budget;
-  // layout: root | acc | lines
-  r->lds_off_acc = (uint32_t)root_b;
-  r->lds_off_lines = (uint32_t)used;
-  r->lds_bytes = (uint32_t)(used + (r->lines_in_lds ? line_b : 0));
+  // layout: root | stage | acc | lines
+  r->lds_off_stage = (uint32_t)root_b;
+  r->lds_off_acc = (uint32_t)(root_b + kStageBytes);
+  r->lds_off_lines = (uint32_t)(used + kStageBytes);
+  r->lds_bytes = (uint32_t)(used + kStageBytes + (r->lines_in_lds ? line_b : 0));
 }
 
 }  // namespace gnm
@@ -304,11 +307,11 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   if (opts) o = *opts;
   const uint32_t root_bits = o.root_bits ? o.root_bits : 12u;
   const uint32_t list_max = o.list_max ? o.list_max : kLineKeys;
-  const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsMax;
+  const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsBudgetMax;
   if (root_bits < 8 || root_bits > 14) return fail(GNM_E_INVAL, "root_bits must be 8..14");
   if (list_max < 2 || list_max > kLineKeys) return fail(GNM_E_INVAL, "list_max must be 2..8");
-  if (lds_budget > kLdsMax || lds_budget < (8u << root_bits))
-    return fail(GNM_E_INVAL, "lds_bytes cannot hold the root table");
+  if (lds_budget > kLdsBudgetMax || lds_budget < (8u << root_bits))
+    return fail(GNM_E_INVAL, "lds_bytes must hold the root table and be at most 147456");
 
   gnm_registry *r = new (std::nothrow) gnm_registry();
   if (!r) return fail(GNM_E_NOMEM, "host allocation failed");
