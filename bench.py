@@ -15,14 +15,17 @@ Beside the headline line, the other forms:
   the default launch shape, then autotuned and replayed as a HIP graph;
 * batched-256: 256 windows of uniform 10 k..2 M records (64-site registry) in
   one autotuned, graph-replayed launch;
+* large-table: 10 windows of 10 M records against 1,000,000 prefixes /
+  20,000 sites (lookup structure and tables beyond LDS), autotuned and
+  graph-replayed;
 * served: open-loop Poisson arrivals (200 windows/s, lognormal sizes with
   median 300 k records, capped at 5 M) through the request loop, host records
   copied in over PCIe; p50/p99 latency from scheduled arrival to result;
   then the same with the record pool already in device memory.
 
 The CPU oracle is timed on the host's cores on one full window; the GPU
-tables are compared with it bit for bit (plain, batched, sampled batched-256
-and served windows).  Prints one JSON line on stdout; progress goes to stderr.
+tables are compared with it bit for bit (plain, batched, sampled batched-256,
+large-table and served windows).  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -45,6 +48,8 @@ PEAK_HBM_GBS = 8000.0      # MI355X HBM3E peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_classify_plain_large.txt")
 POOL_STREAMS = 5           # 64-site record pool: 5 x 10 M records
 POOL_STREAM_BASE = 100
+TABLE_WINDOWS = 10         # large-table: 10 x 10 M records
+TABLE_STREAM_BASE = 200
 
 
 def log(*a):
@@ -167,7 +172,8 @@ def main():
     ap.add_argument("--no-workspace", action="store_true", help="merge tables with atomics only")
     ap.add_argument("--served-seconds", type=float, default=10.0, help="length of the served run (60 = full)")
     ap.add_argument("--served-rate", type=float, default=200.0)
-    ap.add_argument("--gen-workers", type=int, default=8)
+    ap.add_argument("--gen-workers", type=int, default=12)
+    ap.add_argument("--no-large-table", action="store_true", help="skip the 1,000,000-prefix leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (scale for FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -183,8 +189,12 @@ def main():
     jobs = [(flowgen.PLAIN_LARGE, None, k) for k in range(args.windows)]
     if not args.no_forms:
         jobs += [(flowgen.PLAIN_SMALL, 10_000_000, POOL_STREAM_BASE + k) for k in range(POOL_STREAMS)]
+        if not args.no_large_table:
+            jobs += [(flowgen.LARGE_TABLE, 10_000_000, TABLE_STREAM_BASE + k) for k in range(TABLE_WINDOWS)]
     runs = generate(jobs, args.gen_workers)
-    parts, pool_parts = runs[:args.windows], runs[args.windows:]
+    parts = runs[:args.windows]
+    pool_parts = runs[args.windows:args.windows + POOL_STREAMS]
+    table_parts = runs[args.windows + POOL_STREAMS:]
     log("generated %d record runs in %.1fs" % (len(runs), time.time() - t_gen))
 
     import torch
@@ -357,6 +367,44 @@ def main():
         flags256_h = flags256.cpu().numpy().reshape(256, reg1_h.n_sites).copy()
         del g2
 
+        # ------------------------------------------------------------ large-table
+        if table_parts:
+            reg5_h = flowgen.registry_for(flowgen.LARGE_TABLE)
+            t5 = time.time()
+            reg5 = gnm.Registry.from_generated(reg5_h)
+            t5 = time.time() - t5
+            big5 = flowgen.concat(table_parts)
+            d5 = {}
+            for f in ("src_ip", "dst_ip", "packets", "first_ms", "last_ms"):
+                d5[f] = torch.from_numpy(getattr(big5, f).view(np.int32)).to(dev)
+            d5["bytes"] = torch.from_numpy(big5.bytes.view(np.int64)).to(dev)
+            off5 = torch.from_numpy(big5.window_offsets.view(np.int64)).to(dev)
+            s5 = gnm.records_struct(d5, big5.n)
+            nw5 = len(table_parts)
+            acc5 = torch.empty((nw5, reg5.rows, 8), dtype=torch.int64, device=dev)
+            flags5 = torch.empty(nw5 * reg5_h.n_sites, dtype=torch.uint8, device=dev)
+            ws5 = gnm.make_workspace(reg5, device=dev)
+            tp5 = tune.tuned_params(reg5, s5, acc5, window_offsets=off5, n_windows=nw5, n=big5.n, workspace=ws5)
+            g5 = gnm.Graph(reg5, s5, acc5, window_offsets=off5, n_windows=nw5, flags=flags5,
+                           records_per_thread=tp5["records_per_thread"], grid_blocks=tp5["grid_blocks"],
+                           workspace=ws5)
+            g5.launch()
+            wall5, g5ms = timed_events(g5.launch, max(3, args.batched_steps // 2), torch)
+            g5k = float(np.mean(g5ms))
+            i5 = reg5.info()
+            forms["large_table"] = {
+                "windows": nw5, "records": big5.n, "records_per_s": len(g5ms) * big5.n / wall5,
+                "step_ms_avg": g5k, "kernel_gb_s": big5.n * ALG_BYTES_PER_RECORD / (g5k * 1e-3) / 1e9,
+                "launch": "hipGraph replay (classify + flag)", "records_per_thread": tp5["records_per_thread"],
+                "grid_blocks": tp5["grid_blocks"], "registry": "20,000 sites / 1,000,000 prefixes",
+                "registry_build_s": t5, "acc_in_lds": i5["acc_in_lds"], "lines_in_lds": i5["lines_in_lds"],
+                "wide_nodes": i5["n_nodes"], "leaf_lines": i5["n_leaf_lines"], "device_bytes": i5["device_bytes"]}
+            log("large-table (%d records): %.4f ms/step -> %.1f GB/s (registry build %.1fs)" %
+                (big5.n, g5k, forms["large_table"]["kernel_gb_s"], t5))
+            acc5_h = gnm.acc_to_numpy(acc5)[[0, nw5 - 1]].copy()
+            flags5_h = flags5.cpu().numpy().reshape(nw5, reg5_h.n_sites)[[0, nw5 - 1]].copy()
+            del g5, d5, s5
+
         # ------------------------------------------------------------ served
         pinned = {}
         for f in ("src_ip", "dst_ip", "packets", "first_ms", "last_ms", "bytes"):
@@ -419,6 +467,13 @@ def main():
                 if not (acc256_h[w] == e).all() or not (flags256_h[w] == oracle.flags(e, reg1_h.n_sites)).all():
                     bad.append("batched-256 window %d" % w)
             parity_notes["batched_256_windows_checked"] = len(sample)
+            if table_parts:
+                orc5 = oracle.Registry.from_generated(reg5_h)
+                for j, w in enumerate((0, len(table_parts) - 1)):
+                    e = orc5.classify_aggregate(table_parts[w])
+                    if not (acc5_h[j] == e).all() or not (flags5_h[j] == oracle.flags(e, reg5_h.n_sites)).all():
+                        bad.append("large-table window %d" % w)
+                parity_notes["large_table_windows_checked"] = 2
             for tag, res, offs_, sizes_ in (("served", sv_res, sv_offs, sv_sizes),
                                             ("served resident", svr_res, svr_offs, svr_sizes)):
                 pick = rs.choice(len(res), min(32, len(res)), replace=False)

@@ -122,6 +122,8 @@ typedef struct {
 #define GNM_REG_HOST_ONLY 0x1u   /* gnm_registry_opts.flags: build host structure only */
 #define GNM_REG_FORCE_WIDE 0x2u  /* every multi-interval root cell gets a wide node */
 #define GNM_REG_FORCE_LINES 0x4u /* root cells of <= list_max intervals stay leaf lines */
+#define GNM_REG_SHALLOW 0x8u     /* below the root, cells of 5..list_max intervals are leaf lines, not deeper
+                                    nodes (chosen automatically when deeper nodes would pass 64 MiB) */
 
 /* Registry build options (NULL = defaults). */
 typedef struct {
@@ -131,6 +133,9 @@ typedef struct {
   uint32_t lds_bytes;      /* 0 = automatic (147456); else the LDS budget, at most 147456 bytes, of the
                               root table, accumulator table and leaf lines: what does not fit stays in
                               device memory.  A classify workgroup also uses 16 KiB of LDS for staging. */
+  uint32_t node_bits;      /* 0 = automatic (12, or 8 when 12-bit first-level nodes would pass 256 MiB);
+                              else 4..16 index bits of the wide nodes just below the root (deeper nodes
+                              use 8) */
 } gnm_registry_opts;
 
 /* Facts about a built registry. */
@@ -150,6 +155,9 @@ typedef struct {
   uint32_t lines_in_lds;    /* 1 if leaf lines are staged into LDS */
   uint32_t acc_in_lds;      /* 1 if the whole per-block accumulator table fits LDS */
   uint32_t lds_bytes;       /* LDS a classify workgroup uses */
+  uint32_t cache_slots;     /* acc_in_lds == 0: rows a workgroup caches in LDS (first claim wins; the other
+                               rows update the device table directly) */
+  uint32_t node_bits;       /* index bits of first-level wide nodes */
   uint32_t reserved;
 } gnm_registry_info;
 

@@ -28,6 +28,7 @@ GNM_ACCUMULATE = 0x1
 GNM_REG_HOST_ONLY = 0x1
 GNM_REG_FORCE_WIDE = 0x2
 GNM_REG_FORCE_LINES = 0x4
+GNM_REG_SHALLOW = 0x8
 
 ACC_FIELDS = ("flows", "bytes", "packets", "duration_ms", "bulk_flows",
               "rate_sum_bps", "rate_min_bps", "rate_max_bps")
@@ -67,14 +68,15 @@ class TuneResult(ctypes.Structure):
 
 class RegistryOpts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("root_bits", ctypes.c_uint32),
-                ("list_max", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32)]
+                ("list_max", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32), ("node_bits", ctypes.c_uint32)]
 
 
 class RegistryInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("n_prefixes_in", "n_prefixes", "n_host_bits", "n_duplicates",
                                                "n_intervals", "n_nodes", "n_leaf_lines", "device_bytes")] + \
                [(n, ctypes.c_uint32) for n in ("n_sites", "n_local_ranges", "root_bits", "list_max",
-                                               "lines_in_lds", "acc_in_lds", "lds_bytes", "reserved")]
+                                               "lines_in_lds", "acc_in_lds", "lds_bytes", "cache_slots",
+                                               "node_bits", "reserved")]
 
     def as_dict(self) -> Dict[str, int]:
         return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
@@ -174,14 +176,16 @@ class Registry:
 
     def __init__(self, addr, length, site, n_sites: int, local_addr=(), local_len=(),
                  root_bits: int = 0, list_max: int = 0, lds_bytes: int = 0,
-                 host_only: bool = False, stream=None, layout: str = "auto"):
-        """layout: "auto", "wide" (GNM_REG_FORCE_WIDE) or "lines" (GNM_REG_FORCE_LINES)."""
+                 host_only: bool = False, stream=None, layout: str = "auto", node_bits: int = 0):
+        """layout: "auto", "wide" (GNM_REG_FORCE_WIDE), "lines" (GNM_REG_FORCE_LINES),
+        "shallow" (GNM_REG_SHALLOW) or "wide-shallow" (both)."""
         L = lib()
         sites, n = _prefix_array(addr, length, site)
         local, nl = _prefix_array(local_addr, local_len)
         flags = (GNM_REG_HOST_ONLY if host_only else 0) | \
-            {"auto": 0, "wide": GNM_REG_FORCE_WIDE, "lines": GNM_REG_FORCE_LINES}[layout]
-        opts = RegistryOpts(flags, root_bits, list_max, lds_bytes)
+            {"auto": 0, "wide": GNM_REG_FORCE_WIDE, "lines": GNM_REG_FORCE_LINES, "shallow": GNM_REG_SHALLOW,
+             "wide-shallow": GNM_REG_FORCE_WIDE | GNM_REG_SHALLOW}[layout]
+        opts = RegistryOpts(flags, root_bits, list_max, lds_bytes, node_bits)
         h = ctypes.c_void_p()
         st = ctypes.c_void_p(0) if host_only else _stream_handle(stream)
         _check(L.gnm_registry_build(sites, n, int(n_sites), local, nl, ctypes.byref(opts), st,

@@ -15,7 +15,8 @@
 //                       = sub-block j entirely local, bit 16 + j = partly
 //                       local, decided by the local ranges);
 //   wide[]              inner nodes: arrays of 16-byte entries indexed by the
-//                       next up-to-8 address bits;
+//                       next address bits (node_bits of them just below the
+//                       root, up to 8 further down);
 //   lines[]             leaf lines of 64 bytes for cells holding 2..8
 //                       intervals: 8 sorted interval starts (the first is the
 //                       cell's base address) then their 8 site codes; unused
@@ -27,16 +28,19 @@
 //   LINE (0): index of the cell's leaf line;
 //   NODE (1): index (in 16-byte entries) of the cell's wide node.
 // Wide-node entry, four 32-bit words x, y, z, w; kind = y >> 30:
-//   LEAF (2): z = site code;
+//   LEAF (2): z = site code (only when site codes need more than 16 bits;
+//             otherwise a leaf is a QUAD with offsets 0 and four equal codes);
 //   LINE (0): z = leaf line index;
 //   NODE (1): z = index of the next wide node;
-//   QUAD (3): up to 4 intervals of a cell of at most 2^16 addresses:
+//   QUAD (3): up to 4 intervals of a cell of at most 2^16 addresses (or
+//             one interval of any cell):
 //             starts as offsets from the cell base k1 = x & 0xFFFF,
 //             k2 = x >> 16, k3 = y & 0xFFFF (k0 = 0 implicit), sites as
 //             16-bit codes s0 = z & 0xFFFF, s1 = z >> 16, s2 = w & 0xFFFF,
 //             s3 = w >> 16; unused slots repeat the last interval.
 // A node below a cell that leaves `shift` address bits unresolved indexes
-// min(8, shift) bits; its children then leave shift - that many.  Entry 0 of
+// min(node_bits, shift) bits just below the root and min(8, shift) bits
+// further down; its children then leave shift - that many.  Entry 0 of
 // wide[] and line 0 of lines[] are dummies (site 0) that are never referenced
 // by the trie; lanes with no lookup to do read them instead of branching.
 
@@ -54,7 +58,13 @@ constexpr uint32_t kKindQuad = 3u;  // wide-node entries only
 constexpr uint32_t kPayloadMask = (1u << 30) - 1u;
 constexpr uint32_t kLineKeys = 8;     // interval starts per leaf line
 constexpr uint32_t kLineWords = 16;   // 8 starts + 8 site codes = 64 bytes
-constexpr uint32_t kNodeStrideMax = 8;
+constexpr uint32_t kNodeStrideMax = 8;    // index bits of wide nodes below the first level
+constexpr uint32_t kNodeStride1Max = 12;  // index bits of first-level nodes (just below the root)
+// first-level node bytes above which the automatic layout uses 8-bit first-level nodes
+constexpr uint64_t kLevel1Bytes = 256ull << 20;
+// bytes of wide nodes below the first level above which cells of <=
+// list_max intervals there use leaf lines rather than deeper nodes
+constexpr uint64_t kDeepNodeBytes = 64ull << 20;
 
 constexpr uint32_t kMaxLocalRanges = 32;
 constexpr uint32_t kLocalSubBlocks = 16;  // locality sub-blocks per root cell
@@ -74,6 +84,7 @@ constexpr uint32_t kLdsBudgetMax = kLdsMax - kStageBytes;
 enum AccField : uint32_t { kCnt = 0, kBytes, kPackets, kDur, kRateSum, kRateMin, kRateMax, kAccFields };
 
 constexpr uint64_t kMaxRecordsPerFlush = 1ull << 31;
+constexpr uint32_t kMaxCacheSlots = 4096;  // LDS cache of a table too large for LDS
 
 inline uint32_t make_leaf(uint32_t site) { return (kKindLeaf << kKindShift) | site; }
 inline uint32_t make_line(uint32_t index) { return (kKindLine << kKindShift) | index; }

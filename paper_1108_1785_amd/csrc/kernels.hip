@@ -71,9 +71,10 @@ struct ClassifyArgs {
   u64 *acc;  // n_windows * rows * 8 words
   gu64 *root;  // trie entry | locality masks << 32
   gu32 *wide, *lines;
-  uint32_t root_bits;
+  uint32_t root_bits, node_bits;
   uint32_t n_line_words;
   uint32_t lds_off_stage, lds_off_acc, lds_off_lines;
+  uint32_t cache_slots;  // LDS cache slots for a table that does not fit in LDS
   u64 *ws;             // NULL: every table is flushed with atomics
   uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
   LocalRanges local;
@@ -88,13 +89,6 @@ __device__ __forceinline__ bool in_ranges(const LocalRanges &L, uint32_t ip) {
 }
 
 
-// Site of offset `off` in a QUAD wide-node entry.
-__device__ __forceinline__ uint32_t quad_site(u32x4 q, uint32_t off) {
-  const uint32_t pos = ((q.x & 0xFFFFu) <= off) + ((q.x >> 16) <= off) + ((q.y & 0xFFFFu) <= off);
-  const uint32_t lo = pos & 2u ? q.w : q.z;
-  return pos & 1u ? lo >> 16 : lo & 0xFFFFu;
-}
-
 // Longest-prefix match of R addresses at once, from the root trie entries of
 // their cells: site codes of the intervals containing ip[k] for lanes with
 // act[k].  The R walks advance in lockstep
@@ -102,10 +96,16 @@ __device__ __forceinline__ uint32_t quad_site(u32x4 q, uint32_t off) {
 // costs one 16-byte read and usually resolves the address; a leaf line costs
 // one 64-byte line read (keys) and one read of the same line (site).  Lanes
 // with nothing to resolve read the dummy entry 0 rather than branching.
-template <int R, bool LINES_LDS>
+//
+// `mid` issues the next tile's address loads.  It runs right after the
+// first-level reads are issued and before their results are used: a wave's
+// loads complete in issue order, so a walk read issued after the (HBM)
+// record loads could not be used before they too had arrived.
+template <int R, bool LINES_LDS, typename Mid>
 __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint32_t (&root_e)[R],
                                              const bool (&act)[R], uint32_t (&site)[R], gu32 *wide,
-                                             const uint32_t *s_lines, gu32 *g_lines, uint32_t root_bits) {
+                                             const uint32_t *s_lines, gu32 *g_lines, uint32_t root_bits,
+                                             uint32_t node_bits, Mid &&mid) {
   uint32_t node[R], line[R];
   bool any = false, any_line = false;
   // every lane still walking at depth d has the same number of unresolved
@@ -121,9 +121,12 @@ __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint
     any |= node[k] != 0u;
     any_line |= line[k] != 0u;
   }
-  // wide nodes: at most ceil(24 / 8) = 3 levels below a root of >= 8 bits
-  for (int depth = 0; depth < 3 && __builtin_amdgcn_ballot_w64(any); ++depth) {
-    const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
+  // wide nodes: first level node_bits (>= 4) wide, then 8 bits, so at most
+  // 1 + ceil(20 / 8) = 4 levels below a root of >= 8 bits
+  bool mid_done = false;
+  for (int depth = 0; depth < 4 && __builtin_amdgcn_ballot_w64(any); ++depth) {
+    const uint32_t smax = depth == 0 ? node_bits : kNodeStrideMax;
+    const uint32_t ns = shift > smax ? shift - smax : 0u;
     const uint32_t mask = (1u << (shift - ns)) - 1u;
     u32x4 q[R];
 #pragma unroll
@@ -131,41 +134,114 @@ __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint
       const uint32_t idx = node[k] ? (ip[k] >> ns) & mask : 0u;
       q[k] = *(__attribute__((address_space(1))) const u32x4 *)(wide + 4ull * (node[k] + idx));
     }
+    if (depth == 0) {
+      __builtin_amdgcn_sched_barrier(0);
+      mid();
+      __builtin_amdgcn_sched_barrier(0);
+      mid_done = true;
+    }
     shift = ns;
     any = false;
+    // QUAD entries (leaves too, when site codes fit 16 bits) resolve here:
+    // the position is 3 minus the number of split offsets above the
+    // address's offset, each found from the sign of a difference (offsets
+    // are < 2^24); the site is that 16-bit field of z:w.  Selects, not
+    // branches: straight-line code lets the compiler wait for exactly these
+    // reads and not for the record loads issued after them.
+    const uint32_t low = (1u << ns) - 1u;
+    bool odd = false;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      if (!node[k]) continue;
-      const uint32_t kind = q[k].y >> kKindShift;
-      const uint32_t quad = quad_site(q[k], ip[k] & ((1u << ns) - 1u));
-      site[k] = kind == kKindQuad ? quad : q[k].z;
-      line[k] = kind == kKindLine ? q[k].z : 0u;
-      node[k] = kind == kKindNode ? q[k].z : 0u;
-      any |= node[k] != 0u;
-      any_line |= line[k] != 0u;
+      const bool walk = node[k] != 0u;
+      const uint32_t off = ip[k] & low;
+      const uint32_t gt = ((off - (q[k].x & 0xFFFFu)) >> 31) + ((off - (q[k].x >> 16)) >> 31) +
+                          ((off - (q[k].y & 0xFFFFu)) >> 31);
+      const uint64_t packed = ((uint64_t)q[k].w << 32) | q[k].z;
+      const uint32_t qs = (uint32_t)(packed >> (48u - 16u * gt)) & 0xFFFFu;
+      const bool quad = (q[k].y >> kKindShift) == kKindQuad;
+      site[k] = walk && quad ? qs : site[k];
+      odd |= walk && !quad;
+    }
+    // the rest: leaves with wide site codes, leaf lines, deeper nodes
+    if (__builtin_amdgcn_ballot_w64(odd)) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const bool walk = node[k] != 0u;
+        const uint32_t kind = q[k].y >> kKindShift;
+        site[k] = walk && kind == kKindLeaf ? q[k].z : site[k];
+        line[k] = walk && kind == kKindLine ? q[k].z : line[k];
+        node[k] = walk && kind == kKindNode ? q[k].z : 0u;
+        any |= node[k] != 0u;
+        any_line |= line[k] != 0u;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < R; ++k) node[k] = 0u;
     }
   }
+  if (!mid_done) mid();
   // leaf lines: position = number of starts 1..7 that are <= ip
-  if (LINES_LDS || __builtin_amdgcn_ballot_w64(any_line)) {
+  if (LINES_LDS) {
+    // LDS: the keys, then the one site code at the position
+    if (!__builtin_amdgcn_ballot_w64(any_line)) return;
     u32x4 k0[R], k1[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const uint32_t w = line[k] * kLineWords;
-      if (LINES_LDS) {
-        k0[k] = *(const u32x4 *)(s_lines + w);
-        k1[k] = *(const u32x4 *)(s_lines + w + 4);
-      } else {
-        k0[k] = *(__attribute__((address_space(1))) const u32x4 *)(g_lines + w);
-        k1[k] = *(__attribute__((address_space(1))) const u32x4 *)(g_lines + w + 4);
-      }
+      k0[k] = *(const u32x4 *)(s_lines + w);
+      k1[k] = *(const u32x4 *)(s_lines + w + 4);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const uint32_t x = ip[k];
       const uint32_t pos = (k0[k].y <= x) + (k0[k].z <= x) + (k0[k].w <= x) + (k1[k].x <= x) +
                            (k1[k].y <= x) + (k1[k].z <= x) + (k1[k].w <= x);
-      const uint32_t w = line[k] * kLineWords + kLineKeys + pos;
-      const uint32_t ls = LINES_LDS ? s_lines[w] : g_lines[w];
+      const uint32_t ls = s_lines[line[k] * kLineWords + kLineKeys + pos];
+      if (line[k]) site[k] = ls;
+    }
+  } else if (R == 4) {
+    // device memory, four walks per lane: the keys, then the one site code
+    // (the whole line for four walks at once would not fit the registers)
+    if (!__builtin_amdgcn_ballot_w64(any_line)) return;
+    u32x4 k0[R], k1[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      typedef __attribute__((address_space(1))) const u32x4 gq;
+      const gq *l = (const gq *)(g_lines + line[k] * kLineWords);
+      k0[k] = l[0];
+      k1[k] = l[1];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint32_t x = ip[k];
+      const uint32_t pos = (k0[k].y <= x) + (k0[k].z <= x) + (k0[k].w <= x) + (k1[k].x <= x) +
+                           (k1[k].y <= x) + (k1[k].z <= x) + (k1[k].w <= x);
+      const uint32_t ls = g_lines[line[k] * kLineWords + kLineKeys + pos];
+      if (line[k]) site[k] = ls;
+    }
+  } else if (__builtin_amdgcn_ballot_w64(any_line)) {
+    // device memory: the whole 64-byte line in one round trip, the site
+    // code selected in registers
+    u32x4 k0[R], k1[R], s0[R], s1[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      typedef __attribute__((address_space(1))) const u32x4 gq;
+      const gq *l = (const gq *)(g_lines + line[k] * kLineWords);
+      k0[k] = l[0];
+      k1[k] = l[1];
+      s0[k] = l[2];
+      s1[k] = l[3];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint32_t x = ip[k];
+      const uint32_t hi = k1[k].x <= x;  // position >= 4
+      const u32x4 kk = hi ? k1[k] : k0[k];
+      const u32x4 ss = hi ? s1[k] : s0[k];
+      // position within the half: starts 1..3 of that half that are <= ip
+      // (start 0 of the low half is the cell start, <= ip by construction)
+      const uint32_t p = (kk.y <= x) + (kk.z <= x) + (kk.w <= x);
+      const uint32_t ls = p == 0 ? ss.x : (p == 1 ? ss.y : (p == 2 ? ss.z : ss.w));
       if (line[k]) site[k] = ls;
     }
   }
@@ -223,37 +299,83 @@ __device__ __forceinline__ uint32_t window_of(const ClassifyArgs &a, uint64_t i,
 
 // ---------------------------------------------------------------- accumulation
 
+struct Lds {
+  const uint64_t *root;
+  const uint32_t *lines;
+  u64 *acc;        // the accumulator table, or the cache slots' rows
+  u32x4 *stage;    // this wave's kStageEntries staging entries
+  uint32_t *tags;  // cache slots: row + 1 of the owner, 0 = free
+  uint32_t slots;  // cache slots (0 when the table is in LDS)
+};
+
+// Staging code of a record whose row lives in an LDS cache slot.
+constexpr uint32_t kInSlot = 0x80000000u;
+
+// LDS cache slot of a row (any slot count): multiplicative hash, then the
+// high half of hash * slots.
+__device__ __forceinline__ uint32_t cache_slot(uint32_t row, uint32_t slots) {
+  return __umulhi(row * 0x9E3779B1u, slots);
+}
+
 // Fields every record updates (the bulk count rides in the packed `cnt`).
+// With the whole table in LDS the row is the LDS row.  Otherwise (a table
+// too large for LDS) the row goes to an LDS cache slot: a slot belongs to the
+// first row that claims it in this workgroup's current window segment, and
+// records of rows that find their slot taken update the device table with
+// device-scope atomics.  Returns the code the bulk pass needs: the LDS row,
+// kInSlot | slot, or the device-table row.
 template <bool ACC_LDS>
-__device__ __forceinline__ void accumulate(u64 *s_acc, u64 *g_row, uint32_t row, uint64_t b, uint32_t pk,
-                                           uint32_t dur, bool bulk) {
+__device__ __forceinline__ uint32_t accumulate(const Lds &L, u64 *g_row, uint32_t row, uint64_t b, uint32_t pk,
+                                               uint32_t dur, bool bulk) {
   if (ACC_LDS) {
-    u64 *t = s_acc + row * kAccFields;  // one address, immediate field offsets
+    u64 *t = L.acc + row * kAccFields;  // one address, immediate field offsets
     atomicAdd(&t[kCnt], 1ull | ((u64)bulk << 32));
     atomicAdd(&t[kBytes], (u64)b);
     atomicAdd(&t[kPackets], (u64)pk);
     atomicAdd(&t[kDur], (u64)dur);
-  } else {
-    u64 *g = g_row + (uint64_t)row * 8u;
-    atomicAdd(&g[0], 1ull);
-    atomicAdd(&g[1], (u64)b);
-    atomicAdd(&g[2], (u64)pk);
-    atomicAdd(&g[3], (u64)dur);
+    return row;
   }
+  bool hit = false;
+  uint32_t slot = 0;
+  if (L.slots) {
+    slot = cache_slot(row, L.slots);
+    const uint32_t tag = row + 1u;
+    const uint32_t cur = L.tags[slot];
+    hit = cur == tag;
+    if (cur == 0u) {
+      const uint32_t old = atomicCAS(&L.tags[slot], 0u, tag);
+      hit = old == 0u || old == tag;
+    }
+  }
+  if (hit) {
+    u64 *t = L.acc + slot * kAccFields;
+    atomicAdd(&t[kCnt], 1ull | ((u64)bulk << 32));
+    atomicAdd(&t[kBytes], (u64)b);
+    atomicAdd(&t[kPackets], (u64)pk);
+    atomicAdd(&t[kDur], (u64)dur);
+    return kInSlot | slot;
+  }
+  u64 *g = g_row + (uint64_t)row * 8u;
+  atomicAdd(&g[0], 1ull);
+  atomicAdd(&g[1], (u64)b);
+  atomicAdd(&g[2], (u64)pk);
+  atomicAdd(&g[3], (u64)dur);
+  return row;
 }
 
 // Rates of the bulk records a wave has staged (entry: bytes lo, bytes hi,
-// duration, row), one per lane, and their rate fields.  Only about one record
-// in six is bulk, so the wave computes the division once for up to 64 staged
-// records instead of once per record slot of every lane.
+// duration, code from accumulate), one per lane, and their rate fields.
+// Only about one record in six is bulk, so the wave computes the division
+// once for up to 64 staged records instead of once per record slot of every
+// lane.
 template <bool ACC_LDS>
 __device__ __forceinline__ void drain_bulk(const u32x4 *stage, uint32_t count, u64 *s_acc, u64 *g_row) {
   const uint32_t lane = threadIdx.x & 63u;
   if (lane < count) {
     const u32x4 e = stage[lane];
     const uint64_t rate = rate_bps((uint64_t)e.x | ((uint64_t)e.y << 32), e.z);
-    if (ACC_LDS) {
-      u64 *t = s_acc + e.w * kAccFields;
+    if (ACC_LDS || (e.w & kInSlot)) {
+      u64 *t = s_acc + (e.w & ~kInSlot) * kAccFields;
       atomicAdd(&t[kRateSum], (u64)rate);
       atomicMin(&t[kRateMin], (u64)rate);
       atomicMax(&t[kRateMax], (u64)rate);
@@ -294,6 +416,34 @@ __device__ __forceinline__ void flush_atomic(u64 *s_acc, u64 *__restrict__ g, ui
   __syncthreads();
 }
 
+// Flush the LDS cache slots into window table g with device-scope atomics and
+// free them.
+__device__ __forceinline__ void flush_cache(const Lds &L, u64 *__restrict__ g) {
+  __syncthreads();
+  for (uint32_t sl = threadIdx.x; sl < L.slots; sl += kThreads) {
+    const uint32_t tag = L.tags[sl];
+    if (tag == 0u) continue;
+    u64 *t = L.acc + sl * kAccFields;
+    u64 *o = g + (uint64_t)(tag - 1u) * 8u;
+    const u64 cnt = t[kCnt];
+    atomicAdd(&o[0], cnt & 0xFFFFFFFFull);
+    atomicAdd(&o[1], t[kBytes]);
+    atomicAdd(&o[2], t[kPackets]);
+    atomicAdd(&o[3], t[kDur]);
+    const u64 nb = cnt >> 32;
+    if (nb) {
+      atomicAdd(&o[4], nb);
+      atomicAdd(&o[5], t[kRateSum]);
+      atomicMin(&o[6], t[kRateMin]);
+      atomicMax(&o[7], t[kRateMax]);
+    }
+    t[kCnt] = t[kBytes] = t[kPackets] = t[kDur] = t[kRateSum] = t[kRateMax] = 0;
+    t[kRateMin] = ~0ull;
+    L.tags[sl] = 0u;
+  }
+  __syncthreads();
+}
+
 // Copy the workgroup's LDS table (same row layout) to its workspace slot and
 // record which window it belongs to.  The kernel ends right after.
 __device__ __forceinline__ void flush_partial(const ClassifyArgs &a, const u64 *s_acc, uint32_t w) {
@@ -323,14 +473,14 @@ struct Rest {
 
 template <int R, bool VEC>
 __device__ __forceinline__ void load_addr(Addr<R> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
+  // Lanes past the end load the range's last records (always valid, since
+  // ranges are non-empty) and are marked invalid: unconditional loads keep
+  // the code straight-line.
   if (VEC) {
     const uint64_t idx = base + 4ull * threadIdx.x;
-    const bool ok = idx < end;  // end is base + a multiple of 4
-    u32x4 s = {0, 0, 0, 0}, d = {0, 0, 0, 0};
-    if (ok) {
-      s = ldg_nt4(a.src + idx);
-      d = ldg_nt4(a.dst + idx);
-    }
+    const bool ok = idx < end;  // end is base + a multiple of 4, and end - 4 >= the range start
+    const uint64_t at = ok ? idx : end - 4;
+    const u32x4 s = ldg_nt4(a.src + at), d = ldg_nt4(a.dst + at);
     t.s[0] = s.x; t.s[1] = s.y; t.s[2] = s.z; t.s[3] = s.w;
     t.d[0] = d.x; t.d[1] = d.y; t.d[2] = d.z; t.d[3] = d.w;
 #pragma unroll
@@ -340,25 +490,21 @@ __device__ __forceinline__ void load_addr(Addr<R> &t, const ClassifyArgs &a, uin
     for (int k = 0; k < R; ++k) {
       const uint64_t idx = base + (uint64_t)k * kThreads + threadIdx.x;
       t.v[k] = idx < end;
-      t.s[k] = t.v[k] ? ldg_nt(a.src + idx) : 0u;
-      t.d[k] = t.v[k] ? ldg_nt(a.dst + idx) : 0u;
+      const uint64_t at = t.v[k] ? idx : end - 1;
+      t.s[k] = ldg_nt(a.src + at);
+      t.d[k] = ldg_nt(a.dst + at);
     }
   }
 }
 
 template <int R, bool VEC>
 __device__ __forceinline__ void load_rest(Rest<R> &t, const ClassifyArgs &a, uint64_t base, uint64_t end) {
+  // (lanes past the end load the range's last records, as in load_addr)
   if (VEC) {
     const uint64_t idx = base + 4ull * threadIdx.x;
-    u32x4 pk = {0, 0, 0, 0}, f = {0, 0, 0, 0}, l = {0, 0, 0, 0};
-    u64x2 b0 = {0, 0}, b1 = {0, 0};
-    if (idx < end) {
-      pk = ldg_nt4(a.packets + idx);
-      f = ldg_nt4(a.first + idx);
-      l = ldg_nt4(a.last + idx);
-      b0 = ldg_nt2(a.bytes + idx);
-      b1 = ldg_nt2(a.bytes + idx + 2);
-    }
+    const uint64_t at = idx < end ? idx : end - 4;
+    const u32x4 pk = ldg_nt4(a.packets + at), f = ldg_nt4(a.first + at), l = ldg_nt4(a.last + at);
+    const u64x2 b0 = ldg_nt2(a.bytes + at), b1 = ldg_nt2(a.bytes + at + 2);
     t.pk[0] = pk.x; t.pk[1] = pk.y; t.pk[2] = pk.z; t.pk[3] = pk.w;
     t.f[0] = f.x; t.f[1] = f.y; t.f[2] = f.z; t.f[3] = f.w;
     t.l[0] = l.x; t.l[1] = l.y; t.l[2] = l.z; t.l[3] = l.w;
@@ -367,11 +513,11 @@ __device__ __forceinline__ void load_rest(Rest<R> &t, const ClassifyArgs &a, uin
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const uint64_t idx = base + (uint64_t)k * kThreads + threadIdx.x;
-      const bool ok = idx < end;
-      t.pk[k] = ok ? ldg_nt(a.packets + idx) : 0u;
-      t.f[k] = ok ? ldg_nt(a.first + idx) : 0u;
-      t.l[k] = ok ? ldg_nt(a.last + idx) : 0u;
-      t.b[k] = ok ? ldg_nt(a.bytes + idx) : 0ull;
+      const uint64_t at = idx < end ? idx : end - 1;
+      t.pk[k] = ldg_nt(a.packets + at);
+      t.f[k] = ldg_nt(a.first + at);
+      t.l[k] = ldg_nt(a.last + at);
+      t.b[k] = ldg_nt(a.bytes + at);
     }
   }
 }
@@ -397,19 +543,12 @@ __device__ __forceinline__ void load_single(Addr<R> &t, Rest<R> &r, const Classi
   }
 }
 
-struct Lds {
-  const uint64_t *root;
-  const uint32_t *lines;
-  u64 *acc;
-  u32x4 *stage;  // this wave's kStageEntries staging entries
-};
 
-// Classify the tile's records (addresses already loaded) and aggregate them.
-// The caller issues the loads of `r` just before, so their latency overlaps
-// the locality tests and the trie walk.
-template <int R, bool LINES_LDS, bool ACC_LDS>
-__device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r, const ClassifyArgs &a,
-                                             const Lds &L, u64 *g_tab) {
+// Classify the tile's records from their addresses: the accumulator row of
+// each (2 * site + direction, or the NODIR row).
+template <int R, bool LINES_LDS, typename Mid>
+__device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyArgs &a, const Lds &L,
+                                              uint32_t (&row)[R], Mid &&mid) {
   const uint32_t rows = a.rows;
   // one root read per endpoint gives its locality and, for the remote one,
   // the first trie entry of its walk
@@ -441,17 +580,31 @@ __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r,
     inbound[k] = ld[k];
     remote[k] = ld[k] ? t.s[k] : t.d[k];
   }
-  lookup_sites<R, LINES_LDS>(remote, re, one, site, a.wide, L.lines, a.lines, a.root_bits);
-  // Per-record fields now; bulk records are compacted into the wave's
-  // staging area (in LDS, written and read by this wave only, in order) and
-  // their rates computed together.
+  lookup_sites<R, LINES_LDS>(remote, re, one, site, a.wide, L.lines, a.lines, a.root_bits, a.node_bits, mid);
+#pragma unroll
+  for (int k = 0; k < R; ++k) row[k] = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
+}
+
+// Aggregate the tile's classified records.  Per-record fields go straight
+// to the table; bulk records are compacted into the wave's staging area (in
+// LDS, written and read by this wave only, in order) and their rates
+// computed together.
+template <int R, bool ACC_LDS>
+__device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uint32_t (&row)[R], const Rest<R> &r,
+                                               const ClassifyArgs &a, const Lds &L, u64 *g_tab) {
   uint32_t fill = 0;  // wave-uniform
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const uint32_t row = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
     const uint32_t dur = r.l[k] - r.f[k];
-    const bool bulk = t.v[k] && r.b[k] > a.bulk_bytes && dur > 0u;
-    if (t.v[k]) accumulate<ACC_LDS>(L.acc, g_tab, row, r.b[k], r.pk[k], dur, bulk);
+    // (bitwise, not short-circuit: no branches)
+    const bool bulk = valid[k] & (r.b[k] > a.bulk_bytes) & (dur != 0u);
+    uint32_t code = row[k];
+    if (ACC_LDS) {
+      // records past the end go to the spare LDS row after the table
+      code = accumulate<true>(L, g_tab, valid[k] ? row[k] : a.rows, r.b[k], r.pk[k], dur, bulk);
+    } else if (valid[k]) {
+      code = accumulate<false>(L, g_tab, row[k], r.b[k], r.pk[k], dur, bulk);
+    }
     const uint64_t m = __builtin_amdgcn_ballot_w64(bulk);
     const uint32_t c = (uint32_t)__builtin_popcountll(m);
     if (fill + c > kStageEntries) {
@@ -460,28 +613,46 @@ __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r,
     }
     if (bulk) {
       const uint32_t pos = fill + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      L.stage[pos] = u32x4{(uint32_t)r.b[k], (uint32_t)(r.b[k] >> 32), dur, row};
+      L.stage[pos] = u32x4{(uint32_t)r.b[k], (uint32_t)(r.b[k] >> 32), dur, code};
     }
     fill += c;
   }
   if (fill) drain_bulk<ACC_LDS>(L.stage, fill, L.acc, g_tab);
 }
 
-// Records [lo, hi) of one window: tiles whose addresses are prefetched one
-// tile ahead; the other fields load when their tile is processed.
+template <int R, bool LINES_LDS, bool ACC_LDS>
+__device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r, const ClassifyArgs &a,
+                                             const Lds &L, u64 *g_tab) {
+  uint32_t row[R];
+  classify_tile<R, LINES_LDS>(t, a, L, row, [] {});
+  aggregate_tile<R, ACC_LDS>(t.v, row, r, a, L, g_tab);
+}
+
+// Records [lo, hi) of one window, software-pipelined over tiles: the next
+// tile's addresses load while this tile's walk reads are in flight (see
+// lookup_sites) and its other fields right after the walk, so their latency
+// overlaps this tile's walk and aggregation and the next tile's root reads.
 template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS>
 __device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &L, u64 *g_tab, uint64_t lo,
                                               uint64_t hi) {
   constexpr uint64_t T = (uint64_t)kThreads * R;
   Addr<R> cur;
+  Rest<R> rc;
   load_addr<R, VEC>(cur, a, lo, hi);
+  load_rest<R, VEC>(rc, a, lo, hi);
   for (uint64_t base = lo; base < hi; base += T) {
-    Rest<R> rest;
-    load_rest<R, VEC>(rest, a, base, hi);
+    // (past the end, the loads read nothing and give zeros)
     Addr<R> nxt;
-    if (base + T < hi) load_addr<R, VEC>(nxt, a, base + T, hi);
-    process_tile<R, LINES_LDS, ACC_LDS>(cur, rest, a, L, g_tab);
+    uint32_t row[R];
+    classify_tile<R, LINES_LDS>(cur, a, L, row, [&] { load_addr<R, VEC>(nxt, a, base + T, hi); });
+    // the other fields once the walk is done: issued before it they would
+    // hold their registers through it
+    __builtin_amdgcn_sched_barrier(0);
+    Rest<R> rn;
+    load_rest<R, VEC>(rn, a, base + T, hi);
+    aggregate_tile<R, ACC_LDS>(cur.v, row, rc, a, L, g_tab);
     cur = nxt;
+    rc = rn;
   }
 }
 
@@ -506,10 +677,14 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   for (uint32_t i = tid; i < nroot; i += kThreads) s_root[i] = a.root[i];
   if (LINES_LDS)
     for (uint32_t i = tid; i < a.n_line_words; i += kThreads) s_lines[i] = a.lines[i];
-  if (ACC_LDS)
-    for (uint32_t i = tid; i < kAccFields * rows; i += kThreads) s_acc[i] = (i % kAccFields == kRateMin) ? ~0ull : 0ull;
+  // the table, or the cache slots' rows and their tags
+  const uint32_t slots = ACC_LDS ? 0u : a.cache_slots;
+  uint32_t *s_tags = (uint32_t *)(s_acc + (uint64_t)slots * kAccFields);
+  const uint32_t acc_words = kAccFields * (ACC_LDS ? rows + 1u : slots);  // + the spare row
+  for (uint32_t i = tid; i < acc_words; i += kThreads) s_acc[i] = (i % kAccFields == kRateMin) ? ~0ull : 0ull;
+  for (uint32_t i = tid; i < slots; i += kThreads) s_tags[i] = 0u;
   __syncthreads();
-  const Lds L{s_root, s_lines, s_acc, (u32x4 *)(lds + a.lds_off_stage) + (tid >> 6) * kStageEntries};
+  const Lds L{s_root, s_lines, s_acc, (u32x4 *)(lds + a.lds_off_stage) + (tid >> 6) * kStageEntries, s_tags, slots};
 
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
@@ -549,6 +724,8 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     if (ACC_LDS) {
       if (seg_end >= hi && a.ws) flush_partial(a, s_acc, w);
       else flush_atomic(s_acc, g_tab, rows);
+    } else if (slots) {
+      flush_cache(L, g_tab);
     }
     i = seg_end;
   }
@@ -774,8 +951,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.woff = (gu64 *)window_offsets; a.n_windows = n_windows; a.rows = (uint32_t)rows;
   a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
   a.root = (gu64 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
-  a.root_bits = reg->root_bits; a.n_line_words = (uint32_t)reg->lines.size();
+  a.root_bits = reg->root_bits; a.node_bits = reg->node_bits; a.n_line_words = (uint32_t)reg->lines.size();
   a.lds_off_stage = reg->lds_off_stage; a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
+  a.cache_slots = reg->acc_in_lds ? 0u : reg->cache_slots;
   if (use_ws) {
     a.ws = (u64 *)p.workspace;
     a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);

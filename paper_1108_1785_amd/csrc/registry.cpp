@@ -96,13 +96,26 @@ std::vector<Interval> resolve(const std::vector<Pfx> &p, uint32_t none) {
   return out;
 }
 
+// index of the interval containing address a (intervals sorted, first starts at 0)
+size_t find_index(const std::vector<Interval> &v, uint64_t a) {
+  size_t lo = 0, hi = v.size();
+  while (hi - lo > 1) {
+    const size_t mid = (lo + hi) / 2;
+    if ((uint64_t)v[mid].start <= a) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 struct Layout {
   const std::vector<Interval> *iv;
   uint32_t list_max;
   bool root_lines;  // root cells with <= list_max intervals become leaf lines
   bool quad_ok;     // site codes fit 16 bits
+  bool deep;        // cells of 5..list_max intervals get deeper nodes, not lines
+  uint32_t stride1; // index bits of first-level nodes
   std::vector<uint32_t> wide, lines;
   uint64_t n_wide_nodes = 0;
+  uint64_t level1_entries = 0, deeper_entries = 0;
   bool overflow = false;
 
   // index of the interval containing address a
@@ -144,32 +157,40 @@ struct Layout {
     const size_t i0 = span(lo, shift, count);
     if (count == 1) return make_leaf((*iv)[i0].site);
     if (root_lines && count <= list_max) return make_line(add_line(lo, i0, count));
-    return make_node(wide_node(lo, shift));
+    return make_node(wide_node(lo, shift, 0));
   }
 
   // wide node for the cell [lo, lo + 2^shift): returns its first entry index
-  uint32_t wide_node(uint64_t lo, uint32_t shift) {
-    const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
+  uint32_t wide_node(uint64_t lo, uint32_t shift, uint32_t depth) {
+    const uint32_t smax = depth == 0 ? stride1 : kNodeStrideMax;
+    const uint32_t ns = shift > smax ? shift - smax : 0u;
     const uint32_t stride = shift - ns;
     const size_t base = wide.size() / 4;
     if (base + ((size_t)1 << stride) > kPayloadMask) { overflow = true; return 0; }
     wide.resize(wide.size() + 4 * ((size_t)1 << stride));
     ++n_wide_nodes;
+    (depth == 0 ? level1_entries : deeper_entries) += (uint64_t)1 << stride;
     for (uint64_t c = 0; c < ((uint64_t)1 << stride); ++c) {
       uint32_t q[4];
-      wide_entry(lo + (c << ns), ns, q);
+      wide_entry(lo + (c << ns), ns, depth, q);
       for (int j = 0; j < 4; ++j) wide[(base + c) * 4 + j] = q[j];
     }
     return (uint32_t)base;
   }
 
   // 16-byte wide-node entry for the cell [lo, lo + 2^shift)
-  void wide_entry(uint64_t lo, uint32_t shift, uint32_t q[4]) {
+  void wide_entry(uint64_t lo, uint32_t shift, uint32_t depth, uint32_t q[4]) {
     size_t count;
     const size_t i0 = span(lo, shift, count);
     const auto &v = *iv;
     q[0] = q[1] = q[2] = q[3] = 0;
-    if (count == 1) {
+    if (count == 1 && quad_ok) {
+      // a leaf as a QUAD entry: split offsets 0, four equal site codes (the
+      // device decodes every QUAD the same way, whatever the offset)
+      const uint32_t st = v[i0].site;
+      q[1] = kKindQuad << kKindShift;
+      q[2] = q[3] = st | (st << 16);
+    } else if (count == 1) {
       q[1] = kKindLeaf << kKindShift;
       q[2] = v[i0].site;
     } else if (count <= 4 && quad_ok && shift <= 16) {
@@ -183,13 +204,14 @@ struct Layout {
       q[1] = k[3] | (kKindQuad << kKindShift);
       q[2] = st[0] | (st[1] << 16);
       q[3] = st[2] | (st[3] << 16);
-    } else if (!quad_ok && count <= list_max) {
-      // 16-bit site codes do not fit: a leaf line (32-bit codes)
+    } else if (count <= list_max && (!quad_ok || !deep)) {
+      // a leaf line (32-bit site codes): when 16-bit codes do not fit, or
+      // when deeper nodes everywhere would outgrow the caches
       q[1] = kKindLine << kKindShift;
       q[2] = add_line(lo, i0, count);
     } else {
       // a deeper wide node, whose entries are again mostly leaves or quads
-      const uint32_t child = wide_node(lo, shift);
+      const uint32_t child = wide_node(lo, shift, depth + 1);
       q[1] = kKindNode << kKindShift;
       q[2] = child;
     }
@@ -217,8 +239,9 @@ uint32_t host_lookup(const gnm_registry *r, uint32_t ip) {
   if ((e >> kKindShift) == kKindLeaf) return e & kPayloadMask;
   if ((e >> kKindShift) == kKindLine) return line_site(r, e & kPayloadMask, ip);
   uint32_t base = e & kPayloadMask;
-  for (;;) {
-    const uint32_t ns = shift > kNodeStrideMax ? shift - kNodeStrideMax : 0u;
+  for (uint32_t depth = 0;; ++depth) {
+    const uint32_t smax = depth == 0 ? r->node_bits : kNodeStrideMax;
+    const uint32_t ns = shift > smax ? shift - smax : 0u;
     const uint32_t idx = (ip >> ns) & ((1u << (shift - ns)) - 1u);
     const uint32_t *q = &r->wide[((size_t)base + idx) * 4];
     shift = ns;
@@ -273,21 +296,32 @@ void build_local_masks(gnm_registry *r) {
 // LDS plan for a classify workgroup: the root (with locality masks), then (if
 // it fits) the accumulator table, then (if they fit) the leaf lines.
 void plan_lds(gnm_registry *r, uint32_t lds_budget) {
-  // The budget covers root, accumulator table and leaf lines; the bulk-record
-  // staging area comes on top of it.
+  // The budget covers root, accumulator table (or its cache) and leaf lines;
+  // the bulk-record staging area comes on top of it.
   const uint64_t root_b = 8ull << r->root_bits;
   const uint64_t line_b = 4ull * r->lines.size();
-  const uint64_t acc_b = 8ull * kAccFields * r->rows();
+  const uint64_t acc_b = 8ull * kAccFields * (r->rows() + 1u);  // + a spare row for records past the end
   uint64_t used = root_b;
   r->acc_in_lds = used + acc_b <= lds_budget;
   if (r->acc_in_lds) used += acc_b;
   used = (used + 15u) & ~15ull;  // 16-byte loads of line keys
   r->lines_in_lds = used + line_b <= lds_budget;
-  // layout: root | stage | acc | lines
+  // A table that does not fit gets as many cache slots (a 56-byte row and a
+  // 4-byte tag each) as the rest of the budget holds.
+  uint64_t cache_b = 0;
+  r->cache_slots = 0;
+  if (!r->acc_in_lds) {
+    const uint64_t rest = lds_budget - used - (r->lines_in_lds ? line_b : 0);
+    uint64_t slots = rest / (8ull * kAccFields + 4ull);
+    if (slots > kMaxCacheSlots) slots = kMaxCacheSlots;
+    r->cache_slots = (uint32_t)slots;
+    cache_b = (slots * (8ull * kAccFields + 4ull) + 15u) & ~15ull;
+  }
+  // layout: root | stage | table, or cache rows and tags | lines
   r->lds_off_stage = (uint32_t)root_b;
   r->lds_off_acc = (uint32_t)(root_b + kStageBytes);
-  r->lds_off_lines = (uint32_t)(used + kStageBytes);
-  r->lds_bytes = (uint32_t)(used + kStageBytes + (r->lines_in_lds ? line_b : 0));
+  r->lds_off_lines = (uint32_t)(used + kStageBytes + cache_b);
+  r->lds_bytes = (uint32_t)(r->lds_off_lines + (r->lines_in_lds ? line_b : 0));
 }
 
 }  // namespace gnm
@@ -307,6 +341,7 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   if (opts) o = *opts;
   const uint32_t root_bits = o.root_bits ? o.root_bits : 12u;
   const uint32_t list_max = o.list_max ? o.list_max : kLineKeys;
+  if (o.node_bits && (o.node_bits < 4 || o.node_bits > 16)) return fail(GNM_E_INVAL, "node_bits must be 4..16");
   const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsBudgetMax;
   if (root_bits < 8 || root_bits > 14) return fail(GNM_E_INVAL, "root_bits must be 8..14");
   if (list_max < 2 || list_max > kLineKeys) return fail(GNM_E_INVAL, "list_max must be 2..8");
@@ -376,8 +411,28 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
     build_local_masks(r);
     const bool force_wide = (o.flags & GNM_REG_FORCE_WIDE) != 0;
     const bool force_lines = (o.flags & GNM_REG_FORCE_LINES) != 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      Layout lay{&iv, list_max, !force_wide && attempt == 0, n_sites < 0xFFFFu, {}, {}};
+    // Deeper wide nodes resolve a lookup in one 16-byte read per level, but
+    // each costs 2^stride entries; past kDeepNodeBytes the structure would
+    // no longer stay cache-resident, so cells of up to list_max intervals
+    // below the root become 64-byte leaf lines instead.
+    bool root_lines = !force_wide, deep = (o.flags & GNM_REG_SHALLOW) == 0;
+    // First-level nodes index 12 bits by default, so below a 12-bit root one
+    // 16-byte entry covers a /24 and resolves almost every lookup; they cost
+    // 64 KiB each, and past kLevel1Bytes the automatic layout uses 8 bits.
+    const uint32_t sub_bits = 32u - root_bits;
+    uint32_t stride1 = o.node_bits ? o.node_bits : kNodeStride1Max;
+    if (stride1 > sub_bits) stride1 = sub_bits;
+    if (!o.node_bits) {
+      uint64_t multi = 0;
+      for (uint64_t b = 0; b < ((uint64_t)1 << root_bits); ++b) {
+        const uint64_t lo = b << sub_bits, hi = lo + ((uint64_t)1 << sub_bits) - 1;
+        if (r->n_sites && find_index(iv, hi) != find_index(iv, lo)) ++multi;
+      }
+      if (multi * (16ull << stride1) > kLevel1Bytes) stride1 = std::min(kNodeStrideMax, sub_bits);
+    }
+    r->node_bits = stride1;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+      Layout lay{&iv, list_max, root_lines, n_sites < 0xFFFFu, deep, stride1, {}, {}};
       // entry 0 of each array is a harmless dummy (a leaf of site 0) that lanes
       // with nothing to look up may read instead of branching around the load
       lay.wide.assign(4, 0u);
@@ -392,8 +447,13 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
       r->wide.swap(lay.wide);
       r->lines.swap(lay.lines);
       r->info.n_nodes = lay.n_wide_nodes;
+      if (deep && 16ull * lay.deeper_entries > kDeepNodeBytes) {
+        deep = false;
+        continue;
+      }
       plan_lds(r, lds_budget);
-      if (!lay.root_lines || force_lines || r->lines_in_lds) break;
+      if (!root_lines || force_lines || r->lines_in_lds) break;
+      root_lines = false;
     }
     r->info.n_leaf_lines = r->lines.size() / kLineWords - 1;
   } catch (const std::bad_alloc &) {
@@ -408,6 +468,8 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   r->info.lines_in_lds = r->lines_in_lds;
   r->info.acc_in_lds = r->acc_in_lds;
   r->info.lds_bytes = r->lds_bytes;
+  r->info.cache_slots = r->cache_slots;
+  r->info.node_bits = r->node_bits;
 
   if (o.flags & GNM_REG_HOST_ONLY) {
     *out = r;

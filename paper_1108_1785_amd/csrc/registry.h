@@ -13,6 +13,7 @@ struct gnm_registry {
   uint32_t n_sites = 0;
   uint32_t root_bits = 0;
   uint32_t list_max = 0;
+  uint32_t node_bits = 0;  // index bits of first-level wide nodes
 
   // host copy of the lookup structure (see gnm_internal.h)
   std::vector<uint32_t> root, wide, lines;
@@ -35,6 +36,7 @@ struct gnm_registry {
   bool lines_in_lds = false;
   bool acc_in_lds = false;
   uint32_t lds_off_stage = 0, lds_off_acc = 0, lds_off_lines = 0, lds_bytes = 0;
+  uint32_t cache_slots = 0;  // LDS cache slots when the accumulator table does not fit
 
   uint64_t rows() const { return 2ull * (n_sites + 1ull) + 1ull; }
 };

@@ -87,3 +87,13 @@ def boundary_points(prefixes):
             if 0 <= p <= 0xFFFFFFFF:
                 pts.add(p)
     return sorted(pts)
+
+
+def is_local_np(reg, ips):
+    """Locality of addresses against a generated registry's local prefixes (vectorised)."""
+    ips = np.asarray(ips, dtype=np.uint64)
+    out = np.zeros(ips.shape[0], dtype=bool)
+    for a, L in zip(reg.local_addr.tolist(), reg.local_len.tolist()):
+        m = 0 if L == 0 else (0xFFFFFFFF << (32 - L)) & 0xFFFFFFFF
+        out |= (ips & np.uint64(m)) == np.uint64(a & m)
+    return out

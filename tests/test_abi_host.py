@@ -67,7 +67,7 @@ def test_worked_example_host_lookup():
     assert loc.tolist() == [True, False, False]
 
 
-@pytest.mark.parametrize("layout", ["lines", "wide"])
+@pytest.mark.parametrize("layout", ["lines", "wide", "shallow", "wide-shallow"])
 @pytest.mark.parametrize("root_bits,list_max", [(8, 2), (8, 8), (12, 4), (14, 2), (14, 8), (10, 3)])
 @pytest.mark.parametrize("seed", range(12))
 def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max, layout):
@@ -75,7 +75,9 @@ def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max, l
     n_sites, sites, local = random_tiny_registry(rng, n_prefixes=int(rng.integers(0, 60)))
     if layout == "wide" and seed % 3 == 0:
         n_sites = 70000  # site codes beyond 16 bits: no QUAD entries
-    reg = _host_reg(sites, local, n_sites, root_bits=root_bits, list_max=list_max, layout=layout)
+    node_bits = [0, 4, 6, 8, 12][seed % 5]
+    reg = _host_reg(sites, local, n_sites, root_bits=root_bits, list_max=list_max, layout=layout,
+                    node_bits=node_bits)
     orc = oracle.Registry([s[0] for s in sites], [s[1] for s in sites], [s[2] for s in sites], n_sites,
                           [x[0] for x in local], [x[1] for x in local])
     pts = np.array(boundary_points(sites + [(a, l, 0) for a, l in local]), dtype=np.uint32)
@@ -84,7 +86,7 @@ def test_host_trie_matches_oracle_at_every_boundary(seed, root_bits, list_max, l
     assert loc.tolist() == [brute.is_local(local, int(p)) for p in pts.tolist()]
 
 
-@pytest.mark.parametrize("layout", ["auto", "lines", "wide"])
+@pytest.mark.parametrize("layout", ["auto", "lines", "wide", "shallow", "wide-shallow"])
 def test_host_trie_generated_registries(layout):
     import flowgen
     for wl in (flowgen.PLAIN_SMALL, flowgen.PLAIN_LARGE):
@@ -124,7 +126,8 @@ def test_registry_errors(sites, n_sites, local, code):
 
 
 def test_build_option_errors():
-    for kw in (dict(root_bits=7), dict(root_bits=15), dict(list_max=1), dict(list_max=9)):
+    for kw in (dict(root_bits=7), dict(root_bits=15), dict(list_max=1), dict(list_max=9), dict(node_bits=3),
+               dict(node_bits=17), dict(lds_bytes=147456 + 16)):
         with pytest.raises(gnm.GnmError) as e:
             _host_reg([], [], 1, **kw)
         assert e.value.code == gnm.GNM_E_INVAL
@@ -155,3 +158,44 @@ def test_device_calls_reject_host_only_registry_and_nulls():
     assert L.gnm_acc_rows(None) == 0
     assert L.gnm_registry_free(None) == 0
     reg.close()
+
+
+def test_host_trie_large_table():
+    """1,000,000 BGP-like prefixes over 20,000 sites, in the automatic layout
+    (12-bit first-level nodes) and in the 8-bit shallow one (leaf lines below
+    the first level); every boundary agrees with the oracle."""
+    import flowgen
+    r = flowgen.registry_for(flowgen.LARGE_TABLE)
+    reg = gnm.Registry.from_generated(r, host_only=True)
+    orc = oracle.Registry.from_generated(r)
+    info = reg.info()
+    assert info["n_prefixes"] == 1_000_000 and info["n_sites"] == 20_000
+    assert info["acc_in_lds"] == 0  # 40,003 rows do not fit
+    assert info["node_bits"] == 12 and info["cache_slots"] > 1000
+    pts = np.array(boundary_points(list(zip(r.addr.tolist(), r.length.tolist(), r.site.tolist()))), dtype=np.uint32)
+    assert (reg.lookup_host(pts)[0] == orc.lookup(pts)).all()
+    loc = reg.lookup_host(pts)[1]
+    from tests._helpers import is_local_np
+    assert (loc == is_local_np(r, pts)).all()
+    shallow = gnm.Registry.from_generated(r, host_only=True, layout="shallow", node_bits=8)
+    assert shallow.info()["n_leaf_lines"] > 0
+    assert (shallow.lookup_host(pts)[0] == orc.lookup(pts)).all()
+
+
+@pytest.mark.parametrize("root_bits,node_bits", [(8, 16), (14, 16), (8, 4), (12, 5)])
+def test_host_trie_node_bits_extremes(root_bits, node_bits):
+    rng = np.random.default_rng(4242 + node_bits + root_bits)
+    n_sites, sites, local = random_tiny_registry(rng, n_prefixes=40)
+    reg = _host_reg(sites, local, n_sites, root_bits=root_bits, node_bits=node_bits, layout="wide")
+    assert reg.info()["node_bits"] == min(node_bits, 32 - root_bits)
+    orc = oracle.Registry([s[0] for s in sites], [s[1] for s in sites], [s[2] for s in sites], n_sites,
+                          [x[0] for x in local], [x[1] for x in local])
+    pts = np.array(boundary_points(sites + [(a, l, 0) for a, l in local]), dtype=np.uint32)
+    assert reg.lookup_host(pts)[0].tolist() == orc.lookup(pts).tolist()
+
+
+def test_automatic_first_level_width():
+    import flowgen
+    for wl in (flowgen.PLAIN_LARGE, flowgen.LARGE_TABLE):
+        info = gnm.Registry.from_generated(flowgen.registry_for(wl), host_only=True).info()
+        assert info["node_bits"] == 12

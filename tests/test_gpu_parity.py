@@ -121,7 +121,10 @@ def test_workspace_too_small_falls_back(torch_cuda):
 @pytest.mark.parametrize("kw", [dict(layout="wide"), dict(layout="wide", root_bits=8), dict(layout="lines"),
                                 dict(root_bits=8, list_max=2), dict(root_bits=14, list_max=8),
                                 dict(root_bits=10, list_max=3), dict(lds_bytes=8192 + 256, root_bits=10),
-                                dict(lds_bytes=2048, root_bits=8)])
+                                dict(lds_bytes=2048, root_bits=8), dict(layout="shallow"),
+                                dict(layout="wide-shallow"), dict(layout="wide-shallow", lds_bytes=2048, root_bits=8),
+                                dict(layout="wide-shallow", root_bits=14), dict(node_bits=8),
+                                dict(node_bits=4, root_bits=8), dict(node_bits=16, root_bits=14, layout="wide")])
 def test_registry_layout_variants(torch_cuda, kw):
     say("case: layout", kw)
     s = _small()
@@ -155,7 +158,7 @@ def test_edge_registries_and_records(torch_cuda):
         recs = _edge_records(rng, int(rng.integers(0, 3000)), sites, local)
         bulk = int(rng.choice([0, 1_000_000, 1 << 40]))
         kw = dict(root_bits=int(rng.integers(8, 15)), list_max=int(rng.integers(2, 9)),
-                  layout=str(rng.choice(["auto", "wide", "lines"])))
+                  layout=str(rng.choice(["auto", "wide", "lines", "shallow", "wide-shallow"])))
         reg, orc = _regs(sites, local, n_sites, **kw)
         rec = soa(recs)
         exp = orc.classify_aggregate(rec, bulk)
@@ -308,6 +311,33 @@ def test_sites_beyond_16_bits(torch_cuda):
         exp = orc.classify_aggregate(soa(recs))
         got = run(reg, soa(recs))
         assert (got == exp).all(), diff(got, exp)
+
+
+def test_large_table_batched(torch_cuda):
+    """1,000,000 prefixes / 20,000 sites: lookup structure and accumulator
+    table both beyond LDS (device-memory lines and tables)."""
+    say("case: large-table registry, 3M records in 4 windows (one empty) + one plain window")
+    r = flowgen.registry_for(flowgen.LARGE_TABLE)
+    rec = flowgen.records_for(flowgen.LARGE_TABLE, reg=r, n=3_000_000, stream=7)
+    orc = oracle.Registry.from_generated(r)
+    off = np.array([0, 1_200_000, 1_200_000, 2_999_999, 3_000_000], dtype=np.uint64)
+    exp = orc.classify_aggregate(rec, window_offsets=off)
+    w = rec.slice(0, 1_000_003)
+    exp_w = orc.classify_aggregate(w)
+    # automatic layout (12-bit first level), and 8-bit first level with leaf
+    # lines below it in device memory
+    for kw in (dict(), dict(layout="shallow", node_bits=8)):
+        reg = gnm.Registry.from_generated(r, **kw)
+        info = reg.info()
+        say("  layout", kw, info)
+        assert not info["acc_in_lds"] and info["cache_slots"] > 0
+        for rpt in (0, 1):
+            got = run(reg, rec, window_offsets=off, records_per_thread=rpt, workspace=gnm.make_workspace(reg))
+            assert (got == exp).all(), diff(got, exp)
+        got = run(reg, w)
+        assert (got == exp_w).all()
+        assert (flags(reg, got) == oracle.flags(got, r.n_sites)).all()
+        del reg
 
 
 def test_plain_large_full_size(torch_cuda):
