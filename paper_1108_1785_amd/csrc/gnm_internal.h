@@ -84,7 +84,7 @@ constexpr uint32_t kLdsBudgetMax = kLdsMax - kStageBytes;
 enum AccField : uint32_t { kCnt = 0, kBytes, kPackets, kDur, kRateSum, kRateMin, kRateMax, kAccFields };
 
 constexpr uint64_t kMaxRecordsPerFlush = 1ull << 31;
-constexpr uint32_t kMaxCacheSlots = 4096;  // LDS cache of a table too large for LDS
+constexpr uint32_t kMaxCacheSlots = 4096;  // LDS cache (4-way sets) of a table too large for LDS
 
 inline uint32_t make_leaf(uint32_t site) { return (kKindLeaf << kKindShift) | site; }
 inline uint32_t make_line(uint32_t index) { return (kKindLine << kKindShift) | index; }

@@ -311,19 +311,20 @@ struct Lds {
 // Staging code of a record whose row lives in an LDS cache slot.
 constexpr uint32_t kInSlot = 0x80000000u;
 
-// LDS cache slot of a row (any slot count): multiplicative hash, then the
-// high half of hash * slots.
-__device__ __forceinline__ uint32_t cache_slot(uint32_t row, uint32_t slots) {
-  return __umulhi(row * 0x9E3779B1u, slots);
+// LDS cache set of a row (any set count): multiplicative hash, then the
+// high half of hash * sets.
+__device__ __forceinline__ uint32_t cache_set(uint32_t row, uint32_t sets) {
+  return __umulhi(row * 0x9E3779B1u, sets);
 }
 
 // Fields every record updates (the bulk count rides in the packed `cnt`).
 // With the whole table in LDS the row is the LDS row.  Otherwise (a table
-// too large for LDS) the row goes to an LDS cache slot: a slot belongs to the
-// first row that claims it in this workgroup's current window segment, and
-// records of rows that find their slot taken update the device table with
-// device-scope atomics.  Returns the code the bulk pass needs: the LDS row,
-// kInSlot | slot, or the device-table row.
+// too large for LDS) the row goes to an LDS cache: 4-way sets, each way owned
+// by the first row that claims it in this workgroup's current window segment
+// (ways are claimed in order and never released before the segment ends, so
+// a row holds at most one way); records of rows whose set is full update the
+// device table with device-scope atomics.  Returns the code the bulk pass
+// needs: the LDS row, kInSlot | slot, or the device-table row.
 template <bool ACC_LDS>
 __device__ __forceinline__ uint32_t accumulate(const Lds &L, u64 *g_row, uint32_t row, uint64_t b, uint32_t pk,
                                                uint32_t dur, bool bulk) {
@@ -338,14 +339,19 @@ __device__ __forceinline__ uint32_t accumulate(const Lds &L, u64 *g_row, uint32_
   bool hit = false;
   uint32_t slot = 0;
   if (L.slots) {
-    slot = cache_slot(row, L.slots);
+    const uint32_t set = cache_set(row, L.slots >> 2);
+    uint32_t *tg = L.tags + 4u * set;
     const uint32_t tag = row + 1u;
-    const uint32_t cur = L.tags[slot];
-    hit = cur == tag;
-    if (cur == 0u) {
-      const uint32_t old = atomicCAS(&L.tags[slot], 0u, tag);
-      hit = old == 0u || old == tag;
+    const u32x4 t4 = *(const u32x4 *)tg;
+    uint32_t w[4] = {t4.x, t4.y, t4.z, t4.w};
+    uint32_t way = 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (way == 4u && w[j] == 0u) w[j] = atomicCAS(&tg[j], 0u, tag) ?: tag;  // claimed, or its owner
+      if (way == 4u && w[j] == tag) way = j;
     }
+    hit = way < 4u;
+    slot = 4u * set + way;
   }
   if (hit) {
     u64 *t = L.acc + slot * kAccFields;

@@ -314,6 +314,7 @@ void plan_lds(gnm_registry *r, uint32_t lds_budget) {
     const uint64_t rest = lds_budget - used - (r->lines_in_lds ? line_b : 0);
     uint64_t slots = rest / (8ull * kAccFields + 4ull);
     if (slots > kMaxCacheSlots) slots = kMaxCacheSlots;
+    slots &= ~3ull;  // 4-way sets
     r->cache_slots = (uint32_t)slots;
     cache_b = (slots * (8ull * kAccFields + 4ull) + 15u) & ~15ull;
   }
