@@ -130,9 +130,9 @@ typedef struct {
   uint32_t flags;          /* GNM_REG_HOST_ONLY: no device upload (inspection only) */
   uint32_t root_bits;      /* 0 = automatic (12); else 8..14 bits indexed by the LDS-resident top level */
   uint32_t list_max;       /* 0 = automatic (8); else 2..8 intervals per 64-byte leaf line */
-  uint32_t lds_bytes;      /* 0 = automatic (147456); else the LDS budget, at most 147456 bytes, of the
+  uint32_t lds_bytes;      /* 0 = automatic (163840); else the LDS budget, at most 163840 bytes, of the
                               root table, accumulator table and leaf lines: what does not fit stays in
-                              device memory.  A classify workgroup also uses 16 KiB of LDS for staging. */
+                              device memory */
   uint32_t node_bits;      /* 0 = automatic (12, or 8 when 12-bit first-level nodes would pass 256 MiB);
                               else 4..16 index bits of the wide nodes just below the root (deeper nodes
                               use 8) */

@@ -70,12 +70,6 @@ constexpr uint32_t kMaxLocalRanges = 32;
 constexpr uint32_t kLocalSubBlocks = 16;  // locality sub-blocks per root cell
 constexpr uint32_t kMaxSites = 1u << 28;
 constexpr uint32_t kLdsMax = 160u * 1024u;
-// Per classify workgroup: 16 waves x 64 staged bulk records x 16 bytes, where
-// each wave compacts its bulk records before computing their rates.
-constexpr uint32_t kStageEntries = 64;
-constexpr uint32_t kStageBytes = 16u * kStageEntries * 16u;
-// LDS left for the lookup structure and the accumulator table
-constexpr uint32_t kLdsBudgetMax = kLdsMax - kStageBytes;
 
 // Accumulator table held in LDS by a classify workgroup: rows of kAccFields
 // 64-bit words (56 bytes, so rows fall on 32 distinct banks).  `cnt` packs

@@ -21,10 +21,7 @@
 //     ds_add/ds_min/ds_max_u64);
 //   * an exact integer rate: a correctly rounded f64 quotient, within one of
 //     the answer for 8000*bytes < 2^53, corrected by one integer
-//     multiply-compare; a 64-bit long division covers larger byte counts.
-//     Each wave first compacts its bulk records (about one in six) through
-//     LDS, so the division runs once per 64 bulk records, not once per
-//     record slot;
+//     multiply-compare; a 64-bit long division covers larger byte counts;
 //   * each workgroup's final table written with plain coalesced stores to a
 //     caller workspace and combined by a small reduce kernel (device-scope
 //     atomics, which serialise across the chip, are used only for tables
@@ -49,9 +46,9 @@ typedef __attribute__((address_space(1))) const uint32_t gu32;
 typedef __attribute__((address_space(1))) const uint64_t gu64;
 
 constexpr uint32_t kThreads = 1024;
-static_assert(kStageBytes == (kThreads / 64u) * kStageEntries * 16u, "one staging area per wave");
 constexpr uint32_t kRedWords = 64;   // reduce kernel: table words per workgroup
 constexpr uint32_t kRedGroups = 16;  // reduce kernel: waves, each summing every 16th slot
+constexpr uint32_t kRedUnroll = 8;   // reduce kernel: slot loads in flight per lane
 
 struct LocalRanges {
   uint32_t n;
@@ -73,7 +70,7 @@ struct ClassifyArgs {
   gu32 *wide, *lines;
   uint32_t root_bits, node_bits;
   uint32_t n_line_words;
-  uint32_t lds_off_stage, lds_off_acc, lds_off_lines;
+  uint32_t lds_off_acc, lds_off_lines;
   uint32_t cache_slots;  // LDS cache slots for a table that does not fit in LDS
   u64 *ws;             // NULL: every table is flushed with atomics
   uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
@@ -96,16 +93,11 @@ __device__ __forceinline__ bool in_ranges(const LocalRanges &L, uint32_t ip) {
 // costs one 16-byte read and usually resolves the address; a leaf line costs
 // one 64-byte line read (keys) and one read of the same line (site).  Lanes
 // with nothing to resolve read the dummy entry 0 rather than branching.
-//
-// `mid` issues the next tile's address loads.  It runs right after the
-// first-level reads are issued and before their results are used: a wave's
-// loads complete in issue order, so a walk read issued after the (HBM)
-// record loads could not be used before they too had arrived.
-template <int R, bool LINES_LDS, typename Mid>
+template <int R, bool LINES_LDS>
 __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint32_t (&root_e)[R],
                                              const bool (&act)[R], uint32_t (&site)[R], gu32 *wide,
                                              const uint32_t *s_lines, gu32 *g_lines, uint32_t root_bits,
-                                             uint32_t node_bits, Mid &&mid) {
+                                             uint32_t node_bits) {
   uint32_t node[R], line[R];
   bool any = false, any_line = false;
   // every lane still walking at depth d has the same number of unresolved
@@ -123,7 +115,6 @@ __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint
   }
   // wide nodes: first level node_bits (>= 4) wide, then 8 bits, so at most
   // 1 + ceil(20 / 8) = 4 levels below a root of >= 8 bits
-  bool mid_done = false;
   for (int depth = 0; depth < 4 && __builtin_amdgcn_ballot_w64(any); ++depth) {
     const uint32_t smax = depth == 0 ? node_bits : kNodeStrideMax;
     const uint32_t ns = shift > smax ? shift - smax : 0u;
@@ -134,20 +125,12 @@ __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint
       const uint32_t idx = node[k] ? (ip[k] >> ns) & mask : 0u;
       q[k] = *(__attribute__((address_space(1))) const u32x4 *)(wide + 4ull * (node[k] + idx));
     }
-    if (depth == 0) {
-      __builtin_amdgcn_sched_barrier(0);
-      mid();
-      __builtin_amdgcn_sched_barrier(0);
-      mid_done = true;
-    }
     shift = ns;
     any = false;
     // QUAD entries (leaves too, when site codes fit 16 bits) resolve here:
     // the position is 3 minus the number of split offsets above the
     // address's offset, each found from the sign of a difference (offsets
-    // are < 2^24); the site is that 16-bit field of z:w.  Selects, not
-    // branches: straight-line code lets the compiler wait for exactly these
-    // reads and not for the record loads issued after them.
+    // are < 2^24); the site is that 16-bit field of z:w.
     const uint32_t low = (1u << ns) - 1u;
     bool odd = false;
 #pragma unroll
@@ -179,7 +162,6 @@ __device__ __forceinline__ void lookup_sites(const uint32_t (&ip)[R], const uint
       for (int k = 0; k < R; ++k) node[k] = 0u;
     }
   }
-  if (!mid_done) mid();
   // leaf lines: position = number of starts 1..7 that are <= ip
   if (LINES_LDS) {
     // LDS: the keys, then the one site code at the position
@@ -303,7 +285,6 @@ struct Lds {
   const uint64_t *root;
   const uint32_t *lines;
   u64 *acc;        // the accumulator table, or the cache slots' rows
-  u32x4 *stage;    // this wave's kStageEntries staging entries
   uint32_t *tags;  // cache slots: row + 1 of the owner, 0 = free
   uint32_t slots;  // cache slots (0 when the table is in LDS)
 };
@@ -369,29 +350,20 @@ __device__ __forceinline__ uint32_t accumulate(const Lds &L, u64 *g_row, uint32_
   return row;
 }
 
-// Rates of the bulk records a wave has staged (entry: bytes lo, bytes hi,
-// duration, code from accumulate), one per lane, and their rate fields.
-// Only about one record in six is bulk, so the wave computes the division
-// once for up to 64 staged records instead of once per record slot of every
-// lane.
+// Rate fields of a bulk record, at the place accumulate() returned.
 template <bool ACC_LDS>
-__device__ __forceinline__ void drain_bulk(const u32x4 *stage, uint32_t count, u64 *s_acc, u64 *g_row) {
-  const uint32_t lane = threadIdx.x & 63u;
-  if (lane < count) {
-    const u32x4 e = stage[lane];
-    const uint64_t rate = rate_bps((uint64_t)e.x | ((uint64_t)e.y << 32), e.z);
-    if (ACC_LDS || (e.w & kInSlot)) {
-      u64 *t = s_acc + (e.w & ~kInSlot) * kAccFields;
-      atomicAdd(&t[kRateSum], (u64)rate);
-      atomicMin(&t[kRateMin], (u64)rate);
-      atomicMax(&t[kRateMax], (u64)rate);
-    } else {
-      u64 *g = g_row + (uint64_t)e.w * 8u;
-      atomicAdd(&g[4], 1ull);
-      atomicAdd(&g[5], (u64)rate);
-      atomicMin(&g[6], (u64)rate);
-      atomicMax(&g[7], (u64)rate);
-    }
+__device__ __forceinline__ void add_rate(const Lds &L, u64 *g_row, uint32_t code, uint64_t rate) {
+  if (ACC_LDS || (code & kInSlot)) {
+    u64 *t = L.acc + (code & ~kInSlot) * kAccFields;
+    atomicAdd(&t[kRateSum], (u64)rate);
+    atomicMin(&t[kRateMin], (u64)rate);
+    atomicMax(&t[kRateMax], (u64)rate);
+  } else {
+    u64 *g = g_row + (uint64_t)code * 8u;
+    atomicAdd(&g[4], 1ull);
+    atomicAdd(&g[5], (u64)rate);
+    atomicMin(&g[6], (u64)rate);
+    atomicMax(&g[7], (u64)rate);
   }
 }
 
@@ -552,9 +524,9 @@ __device__ __forceinline__ void load_single(Addr<R> &t, Rest<R> &r, const Classi
 
 // Classify the tile's records from their addresses: the accumulator row of
 // each (2 * site + direction, or the NODIR row).
-template <int R, bool LINES_LDS, typename Mid>
+template <int R, bool LINES_LDS>
 __device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyArgs &a, const Lds &L,
-                                              uint32_t (&row)[R], Mid &&mid) {
+                                              uint32_t (&row)[R]) {
   const uint32_t rows = a.rows;
   // one root read per endpoint gives its locality and, for the remote one,
   // the first trie entry of its walk
@@ -586,19 +558,15 @@ __device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyAr
     inbound[k] = ld[k];
     remote[k] = ld[k] ? t.s[k] : t.d[k];
   }
-  lookup_sites<R, LINES_LDS>(remote, re, one, site, a.wide, L.lines, a.lines, a.root_bits, a.node_bits, mid);
+  lookup_sites<R, LINES_LDS>(remote, re, one, site, a.wide, L.lines, a.lines, a.root_bits, a.node_bits);
 #pragma unroll
   for (int k = 0; k < R; ++k) row[k] = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
 }
 
-// Aggregate the tile's classified records.  Per-record fields go straight
-// to the table; bulk records are compacted into the wave's staging area (in
-// LDS, written and read by this wave only, in order) and their rates
-// computed together.
+// Aggregate the tile's classified records.
 template <int R, bool ACC_LDS>
 __device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uint32_t (&row)[R], const Rest<R> &r,
                                                const ClassifyArgs &a, const Lds &L, u64 *g_tab) {
-  uint32_t fill = 0;  // wave-uniform
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const uint32_t dur = r.l[k] - r.f[k];
@@ -611,54 +579,38 @@ __device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uin
     } else if (valid[k]) {
       code = accumulate<false>(L, g_tab, row[k], r.b[k], r.pk[k], dur, bulk);
     }
-    const uint64_t m = __builtin_amdgcn_ballot_w64(bulk);
-    const uint32_t c = (uint32_t)__builtin_popcountll(m);
-    if (fill + c > kStageEntries) {
-      drain_bulk<ACC_LDS>(L.stage, fill, L.acc, g_tab);
-      fill = 0;
-    }
-    if (bulk) {
-      const uint32_t pos = fill + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      L.stage[pos] = u32x4{(uint32_t)r.b[k], (uint32_t)(r.b[k] >> 32), dur, code};
-    }
-    fill += c;
+    if (bulk) add_rate<ACC_LDS>(L, g_tab, code, rate_bps(r.b[k], dur));
   }
-  if (fill) drain_bulk<ACC_LDS>(L.stage, fill, L.acc, g_tab);
 }
 
 template <int R, bool LINES_LDS, bool ACC_LDS>
 __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r, const ClassifyArgs &a,
                                              const Lds &L, u64 *g_tab) {
   uint32_t row[R];
-  classify_tile<R, LINES_LDS>(t, a, L, row, [] {});
+  classify_tile<R, LINES_LDS>(t, a, L, row);
   aggregate_tile<R, ACC_LDS>(t.v, row, r, a, L, g_tab);
 }
 
-// Records [lo, hi) of one window, software-pipelined over tiles: the next
-// tile's addresses load while this tile's walk reads are in flight (see
-// lookup_sites) and its other fields right after the walk, so their latency
-// overlaps this tile's walk and aggregation and the next tile's root reads.
+// Records [lo, hi) of one window: tiles whose addresses are prefetched one
+// tile ahead; the other fields load when their tile starts, so their latency
+// overlaps the locality tests and the trie walk.  (Measured: prefetching the
+// other fields a tile ahead as well, or in the middle of the walk, gained
+// nothing at 4 waves per SIMD.)
 template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS>
 __device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &L, u64 *g_tab, uint64_t lo,
                                               uint64_t hi) {
   constexpr uint64_t T = (uint64_t)kThreads * R;
   Addr<R> cur;
-  Rest<R> rc;
   load_addr<R, VEC>(cur, a, lo, hi);
-  load_rest<R, VEC>(rc, a, lo, hi);
   for (uint64_t base = lo; base < hi; base += T) {
-    // (past the end, the loads read nothing and give zeros)
+    Rest<R> rest;
+    load_rest<R, VEC>(rest, a, base, hi);
     Addr<R> nxt;
+    load_addr<R, VEC>(nxt, a, base + T, hi);  // past the end: reloads the last records, marked invalid
     uint32_t row[R];
-    classify_tile<R, LINES_LDS>(cur, a, L, row, [&] { load_addr<R, VEC>(nxt, a, base + T, hi); });
-    // the other fields once the walk is done: issued before it they would
-    // hold their registers through it
-    __builtin_amdgcn_sched_barrier(0);
-    Rest<R> rn;
-    load_rest<R, VEC>(rn, a, base + T, hi);
-    aggregate_tile<R, ACC_LDS>(cur.v, row, rc, a, L, g_tab);
+    classify_tile<R, LINES_LDS>(cur, a, L, row);
+    aggregate_tile<R, ACC_LDS>(cur.v, row, rest, a, L, g_tab);
     cur = nxt;
-    rc = rn;
   }
 }
 
@@ -690,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   for (uint32_t i = tid; i < acc_words; i += kThreads) s_acc[i] = (i % kAccFields == kRateMin) ? ~0ull : 0ull;
   for (uint32_t i = tid; i < slots; i += kThreads) s_tags[i] = 0u;
   __syncthreads();
-  const Lds L{s_root, s_lines, s_acc, (u32x4 *)(lds + a.lds_off_stage) + (tid >> 6) * kStageEntries, s_tags, slots};
+  const Lds L{s_root, s_lines, s_acc, s_tags, slots};
 
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
@@ -766,20 +718,32 @@ __global__ __launch_bounds__(kRedWords *kRedGroups) void reduce_partials_kernel(
   const uint32_t words = kAccFields * rows;
   const uint32_t i = tile * kRedWords + lane;
   const uint32_t f = i % kAccFields;
+  const bool is_cnt = f == kCnt, is_min = f == kRateMin, is_max = f == kRateMax;
   // x: sum (or min / max) of the word; y: bulk flows, for the packed count word
-  u64 x = f == kRateMin ? ~0ull : 0ull, y = 0;
+  u64 xs = 0, y = 0, xmin = ~0ull, xmax = 0;
   if (i < words) {
-    const u64 *p = ws + (uint64_t)(b0 + g) * words + i;
-    const uint64_t step = (uint64_t)kRedGroups * words;
-#pragma unroll 4
-    for (uint32_t b = b0 + g; b < b1; b += kRedGroups, p += step) {
-      const u64 v = __builtin_nontemporal_load(p);
-      if (f == kCnt) { x += v & 0xFFFFFFFFull; y += v >> 32; }
-      else if (f == kRateMin) x = v < x ? v : x;
-      else if (f == kRateMax) x = v > x ? v : x;
-      else x += v;
+    const u64 *p = ws + i;
+    // kRedUnroll loads in flight per lane (indexes past the range reload its
+    // last slot and are masked), then branch-free combining
+    for (uint32_t base = b0 + g; base < b1; base += kRedGroups * kRedUnroll) {
+      u64 v[kRedUnroll];
+#pragma unroll
+      for (uint32_t j = 0; j < kRedUnroll; ++j) {
+        const uint32_t b = base + j * kRedGroups;
+        v[j] = __builtin_nontemporal_load(p + (uint64_t)(b < b1 ? b : b1 - 1u) * words);
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kRedUnroll; ++j) {
+        const bool ok = base + j * kRedGroups < b1;
+        const u64 val = v[j];
+        xs += ok ? (is_cnt ? (val & 0xFFFFFFFFull) : val) : 0ull;
+        y += ok && is_cnt ? val >> 32 : 0ull;
+        xmin = ok && val < xmin ? val : xmin;
+        xmax = ok && val > xmax ? val : xmax;
+      }
     }
   }
+  u64 x = is_min ? xmin : (is_max ? xmax : xs);
   __shared__ u64 red[kRedGroups][2][kRedWords];
   red[g][0][lane] = x;
   red[g][1][lane] = y;
@@ -958,7 +922,7 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
   a.root = (gu64 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
   a.root_bits = reg->root_bits; a.node_bits = reg->node_bits; a.n_line_words = (uint32_t)reg->lines.size();
-  a.lds_off_stage = reg->lds_off_stage; a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
+  a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
   a.cache_slots = reg->acc_in_lds ? 0u : reg->cache_slots;
   if (use_ws) {
     a.ws = (u64 *)p.workspace;

@@ -296,8 +296,7 @@ void build_local_masks(gnm_registry *r) {
 // LDS plan for a classify workgroup: the root (with locality masks), then (if
 // it fits) the accumulator table, then (if they fit) the leaf lines.
 void plan_lds(gnm_registry *r, uint32_t lds_budget) {
-  // The budget covers root, accumulator table (or its cache) and leaf lines;
-  // the bulk-record staging area comes on top of it.
+  // The budget covers root, accumulator table (or its cache) and leaf lines.
   const uint64_t root_b = 8ull << r->root_bits;
   const uint64_t line_b = 4ull * r->lines.size();
   const uint64_t acc_b = 8ull * kAccFields * (r->rows() + 1u);  // + a spare row for records past the end
@@ -318,10 +317,9 @@ void plan_lds(gnm_registry *r, uint32_t lds_budget) {
     r->cache_slots = (uint32_t)slots;
     cache_b = (slots * (8ull * kAccFields + 4ull) + 15u) & ~15ull;
   }
-  // layout: root | stage | table, or cache rows and tags | lines
-  r->lds_off_stage = (uint32_t)root_b;
-  r->lds_off_acc = (uint32_t)(root_b + kStageBytes);
-  r->lds_off_lines = (uint32_t)(used + kStageBytes + cache_b);
+  // layout: root | table, or cache rows and tags | lines
+  r->lds_off_acc = (uint32_t)root_b;
+  r->lds_off_lines = (uint32_t)(used + cache_b);
   r->lds_bytes = (uint32_t)(r->lds_off_lines + (r->lines_in_lds ? line_b : 0));
 }
 
@@ -343,11 +341,11 @@ extern "C" int gnm_registry_build(const gnm_prefix *sites, uint64_t n_prefixes, 
   const uint32_t root_bits = o.root_bits ? o.root_bits : 12u;
   const uint32_t list_max = o.list_max ? o.list_max : kLineKeys;
   if (o.node_bits && (o.node_bits < 4 || o.node_bits > 16)) return fail(GNM_E_INVAL, "node_bits must be 4..16");
-  const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsBudgetMax;
+  const uint32_t lds_budget = o.lds_bytes ? o.lds_bytes : kLdsMax;
   if (root_bits < 8 || root_bits > 14) return fail(GNM_E_INVAL, "root_bits must be 8..14");
   if (list_max < 2 || list_max > kLineKeys) return fail(GNM_E_INVAL, "list_max must be 2..8");
-  if (lds_budget > kLdsBudgetMax || lds_budget < (8u << root_bits))
-    return fail(GNM_E_INVAL, "lds_bytes must hold the root table and be at most 147456");
+  if (lds_budget > kLdsMax || lds_budget < (8u << root_bits))
+    return fail(GNM_E_INVAL, "lds_bytes must hold the root table and be at most 163840");
 
   gnm_registry *r = new (std::nothrow) gnm_registry();
   if (!r) return fail(GNM_E_NOMEM, "host allocation failed");

@@ -35,7 +35,7 @@ struct gnm_registry {
   // launch-time LDS plan
   bool lines_in_lds = false;
   bool acc_in_lds = false;
-  uint32_t lds_off_stage = 0, lds_off_acc = 0, lds_off_lines = 0, lds_bytes = 0;
+  uint32_t lds_off_acc = 0, lds_off_lines = 0, lds_bytes = 0;
   uint32_t cache_slots = 0;  // LDS cache slots when the accumulator table does not fit
 
   uint64_t rows() const { return 2ull * (n_sites + 1ull) + 1ull; }

@@ -127,7 +127,7 @@ def test_registry_errors(sites, n_sites, local, code):
 
 def test_build_option_errors():
     for kw in (dict(root_bits=7), dict(root_bits=15), dict(list_max=1), dict(list_max=9), dict(node_bits=3),
-               dict(node_bits=17), dict(lds_bytes=147456 + 16)):
+               dict(node_bits=17), dict(lds_bytes=163840 + 16)):
         with pytest.raises(gnm.GnmError) as e:
             _host_reg([], [], 1, **kw)
         assert e.value.code == gnm.GNM_E_INVAL
