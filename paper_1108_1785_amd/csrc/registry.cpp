@@ -299,7 +299,7 @@ void plan_lds(gnm_registry *r, uint32_t lds_budget) {
   // The budget covers root, accumulator table (or its cache) and leaf lines.
   const uint64_t root_b = 8ull << r->root_bits;
   const uint64_t line_b = 4ull * r->lines.size();
-  const uint64_t acc_b = 8ull * kAccFields * (r->rows() + 1u);  // + a spare row for records past the end
+  const uint64_t acc_b = 8ull * kAccFields * r->rows();
   uint64_t used = root_b;
   r->acc_in_lds = used + acc_b <= lds_budget;
   if (r->acc_in_lds) used += acc_b;
