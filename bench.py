@@ -116,11 +116,14 @@ def timed_events(fn, steps, torch):
     return wall, [a.elapsed_time(b) for a, b in evs]
 
 
-def served_run(gnm, serve, reg, pool_views, pool_n, seconds, rate_hz, seed, log_every=2.0, resident=False):
-    """Open-loop Poisson driver; latency = completion - scheduled arrival."""
+def served_run(gnm, serve, reg, pool_views, pool_n, seconds, rate_hz, seed, log_every=2.0, resident=False,
+               burst=0):
+    """Open-loop Poisson driver; latency = completion - scheduled arrival.
+
+    burst > 0: that many windows all arrive at once instead (saturation)."""
     import flowgen
     rng = np.random.Generator(np.random.PCG64(seed))
-    arr = flowgen.poisson_arrivals(rng, rate_hz, seconds)
+    arr = np.zeros(burst) if burst else flowgen.poisson_arrivals(rng, rate_hz, seconds)
     sizes = flowgen.served_sizes(rng, len(arr))
     offs = (rng.random(len(arr)) * (pool_n - sizes + 1)).astype(np.int64)
     ex = serve.GpuExecutor(reg, mem_budget_bytes=4 << 30, max_batch_windows=1024, max_inflight=2)
@@ -144,9 +147,10 @@ def served_run(gnm, serve, reg, pool_views, pool_n, seconds, rate_hz, seed, log_
     lat = [r_.latency_s * 1e3 for r_ in res]
     total = int(sizes.sum())
     out = {
-        "windows": len(res), "records": total, "seconds": seconds, "arrival_rate_hz": rate_hz,
+        "windows": len(res), "records": total, "seconds": seconds if not burst else t_end - t0,
+        "arrival_rate_hz": rate_hz if not burst else None,
         "records_per_s": total / max(t_end - t0, 1e-9),
-        "offered_records_per_s": total / seconds,
+        "offered_records_per_s": total / seconds if not burst else None,
         "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99), "latency_ms_max": max(lat) if lat else None,
         "launches": int(srv.stats["launches"]),
         "windows_per_launch": len(res) / max(int(srv.stats["launches"]), 1),
@@ -424,6 +428,13 @@ def main():
         log("served (resident): p50 %.3f ms p99 %.3f ms" % (svr["latency_ms_p50"], svr["latency_ms_p99"]))
         forms["served"] = sv
         forms["served_device_resident"] = svr
+        # saturation: a burst of windows at once, from device memory; the
+        # request loop batches whatever has arrived whenever a launch slot frees
+        sat, _, _, _ = served_run(gnm, serve, reg1, pool_dev, pool.n, 0.0, 0.0, flowgen.SEED_BASE + 402,
+                                  resident=True, burst=2000)
+        log("served (burst of 2000): %.3g records/s, %.1f windows/launch, p50 %.1f ms p99 %.1f ms" %
+            (sat["records_per_s"], sat["windows_per_launch"], sat["latency_ms_p50"], sat["latency_ms_p99"]))
+        forms["served_saturation"] = sat
         del pinned
 
     # ---------------------------------------------------------------- oracle
