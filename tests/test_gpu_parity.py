@@ -299,6 +299,30 @@ def test_batched_with_empty_windows(torch_cuda):
     assert (got[0, :, 6] == np.uint64(M64)).all() and (got[0, :, 0] == 0).all()
 
 
+def test_many_tiny_windows(torch_cuda):
+    """20,000 windows of 0..8 records (every workgroup slice crosses hundreds
+    of window boundaries), and offsets past the end, which clamp to n."""
+    say("case: 20000 tiny windows")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rng = np.random.default_rng(2024)
+    sizes = rng.integers(0, 9, size=20_000)
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    np.cumsum(sizes, out=off[1:])
+    rec = s["rec"].slice(0, int(off[-1]))
+    exp = s["orc"].classify_aggregate(rec, window_offsets=off)
+    for grid, ws in ((0, True), (37, False), (1024, True)):
+        got = run(reg, rec, window_offsets=off, grid_blocks=grid,
+                  workspace=gnm.make_workspace(reg, grid) if ws else None)
+        assert (got == exp).all(), diff(got, exp)
+    # offsets beyond the records clamp to n: the last windows are empty
+    off2 = off.copy()
+    off2[-3:] = np.uint64(rec.n + 1000)
+    exp2 = s["orc"].classify_aggregate(rec, window_offsets=np.minimum(off2, np.uint64(rec.n)))
+    got2 = run(reg, rec, window_offsets=off2)
+    assert (got2 == exp2).all(), diff(got2, exp2)
+
+
 def test_sites_beyond_16_bits(torch_cuda):
     say("case: 70000 sites (no 16-bit site codes)")
     rng = np.random.default_rng(77)
