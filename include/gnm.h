@@ -241,8 +241,8 @@ uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks);
  * kernel.  Each classify workgroup walks a balanced contiguous slice of all
  * records, flushing its LDS table at window changes.  Errors: GNM_E_INVAL
  * (null pointers, n_windows = 0, offsets NULL with n_windows > 1,
- * records_per_thread not 0/1/2/4), GNM_E_UNSUPPORTED (host-only registry),
- * GNM_E_HIP (launch failed).
+ * records_per_thread not 0/1/2/4, n_windows tables beyond 2^39 words),
+ * GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
  */
 int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
                            const uint64_t *window_offsets, uint32_t n_windows,
