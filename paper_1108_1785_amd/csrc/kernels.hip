@@ -18,7 +18,8 @@
 //     resolves a lookup; the R lookups of a lane advance in lockstep so their
 //     memory accesses overlap;
 //   * a per-workgroup accumulator table in LDS (rows of seven u64 words,
-//     ds_add/ds_min/ds_max_u64);
+//     ds_add/ds_min/ds_max_u64); a table too large for LDS lives in device
+//     memory behind a 4-way LDS cache of its hot rows;
 //   * an exact integer rate: a correctly rounded f64 quotient, within one of
 //     the answer for 8000*bytes < 2^53, corrected by one integer
 //     multiply-compare; a 64-bit long division covers larger byte counts;
