@@ -16,6 +16,12 @@ Row layout of every result (one row = 8 unsigned 64-bit fields):
   rate_min_bps (2**64-1 when no bulk flow), rate_max_bps.
 Rows are 2*site+dir (dir 0 inbound, 1 outbound) for site 0..S, where S is the
 "no registered site" row, then NODIR = 2*S+2.
+
+Median statistic: `rate_histograms` counts each row's bulk-flow rates in
+10,001 buckets of 10 kbps; `rate_medians` sorts each row's buckets and takes
+the lower median; `median_flags` applies the two-window warning.  They are
+pinned against a per-record brute force and `statistics.median_low`, bucket
+closed forms and hand-worked flag sequences.
 """
 from __future__ import annotations
 
@@ -72,6 +78,9 @@ def lib():
         L.orc_classify_aggregate_windows.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, P, P,
                                                      ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, P]
         L.orc_classify_aggregate_windows.restype = ctypes.c_int
+        L.orc_classify_rows.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, ctypes.c_uint64, ctypes.c_uint64,
+                                        P, P, P]
+        L.orc_classify_rows.restype = ctypes.c_int
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -151,6 +160,101 @@ class Registry:
         if rc != OK:
             raise OracleError(rc)
         return out
+
+
+RATE_BUCKETS = 10001      # 10 kbps buckets; the last one takes every rate above 100 Mbps
+RATE_BUCKET_BPS = 10_000
+NO_MEDIAN = 0xFFFFFFFF
+
+
+def rate_bucket(rate_bps) -> np.ndarray:
+    """Bucket of a rate: floor(rate / 10 kbps), the rates of the last bucket
+    and above all in bucket 10000 (§III.B.2, TransRate Kernel)."""
+    r = np.asarray(rate_bps, dtype=np.uint64)
+    return np.minimum(r // np.uint64(RATE_BUCKET_BPS), np.uint64(RATE_BUCKETS - 1)).astype(np.uint32)
+
+
+def _classify_rows(reg: "Registry", rec, bulk_bytes: int):
+    f = {k: np.ascontiguousarray(getattr(rec, k)) for k in ("src_ip", "dst_ip", "bytes", "first_ms", "last_ms")}
+    n = f["src_ip"].shape[0]
+    row = np.empty(n, dtype=np.uint32)
+    bulk = np.empty(n, dtype=np.uint8)
+    rate = np.empty(n, dtype=np.uint64)
+    rc = lib().orc_classify_rows(reg._h, _p(reg.local_addr), _p(reg.local_len), reg.local_addr.shape[0],
+                                 _p(f["src_ip"]), _p(f["dst_ip"]), _p(f["bytes"]), _p(f["first_ms"]),
+                                 _p(f["last_ms"]), n, bulk_bytes, _p(row), _p(bulk), _p(rate))
+    if rc != OK:
+        raise OracleError(rc)
+    return row, bulk.astype(bool), rate
+
+
+def rate_histograms(reg: "Registry", rec, window_offsets=None, bulk_bytes: int = 1_000_000) -> np.ndarray:
+    """Counts of bulk-flow rates per (window, row, 10 kbps bucket): uint32[n_windows, rows, 10001]."""
+    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes)
+    off = window_offsets if window_offsets is not None else getattr(rec, "window_offsets", None)
+    off = np.array([0, rec.n], dtype=np.uint64) if off is None else np.asarray(off, dtype=np.uint64)
+    nw = off.shape[0] - 1
+    out = np.zeros((nw, reg.rows, RATE_BUCKETS), dtype=np.uint32)
+    for w in range(nw):
+        lo, hi = int(off[w]), int(off[w + 1])
+        bulk = is_bulk[lo:hi]
+        np.add.at(out[w], (row[lo:hi][bulk], rate_bucket(rate[lo:hi][bulk])), 1)
+    return out
+
+
+def rate_medians(reg: "Registry", rec, window_offsets=None, bulk_bytes: int = 1_000_000):
+    """Median bucket and bulk-flow count per (window, row).
+
+    The median of a row's N >= 1 bulk flows is the bucket of its ceil(N/2)-th
+    smallest rate (the lower median), found by sorting the flows' buckets;
+    NO_MEDIAN when N = 0.  Returns (uint32[n_windows, rows], uint64[n_windows, rows]).
+    """
+    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes)
+    off = window_offsets if window_offsets is not None else getattr(rec, "window_offsets", None)
+    off = np.array([0, rec.n], dtype=np.uint64) if off is None else np.asarray(off, dtype=np.uint64)
+    nw = off.shape[0] - 1
+    med = np.full((nw, reg.rows), NO_MEDIAN, dtype=np.uint32)
+    cnt = np.zeros((nw, reg.rows), dtype=np.uint64)
+    for w in range(nw):
+        lo, hi = int(off[w]), int(off[w + 1])
+        bulk = is_bulk[lo:hi]
+        r, b = row[lo:hi][bulk], rate_bucket(rate[lo:hi][bulk])
+        order = np.lexsort((b, r))  # by row, then by bucket
+        r, b = r[order], b[order]
+        rows_present, start, n = np.unique(r, return_index=True, return_counts=True)
+        med[w, rows_present] = b[start + (n + 1) // 2 - 1]
+        cnt[w, rows_present] = n
+    return med, cnt
+
+
+def median_flags(med: np.ndarray, cnt: np.ndarray, n_sites: int, threshold_bps: int = 1_000_000,
+                 min_bulk_flows: int = 0, prev: Optional[np.ndarray] = None) -> np.ndarray:
+    """Median warnings per (window, site), one site and window at a time.
+
+    bit d (d = 0 inbound, 1 outbound): the (site, d) row has at least
+    max(1, min_bulk_flows) bulk flows and its median bucket's lower bound,
+    bucket * 10 kbps, is below the threshold (exactly "median < threshold"
+    when the threshold is a multiple of 10 kbps, as the paper's 1 Mbps is);
+    bit 2 + d: bit d is set in this window and in the previous one (window
+    w - 1, or `prev` for the first window): the paper's warning after two
+    consecutive hours (§III.B.1, NetPerf Monitoring Thread; §IV.B).
+    """
+    med = np.asarray(med)
+    cnt = np.asarray(cnt)
+    nw = med.shape[0]
+    need = max(1, int(min_bulk_flows))
+    out = np.zeros((nw, n_sites), dtype=np.uint8)
+    for w in range(nw):
+        for s in range(n_sites):
+            f = 0
+            for d in (0, 1):
+                m, c = int(med[w, 2 * s + d]), int(cnt[w, 2 * s + d])
+                if c >= need and m * RATE_BUCKET_BPS < threshold_bps:
+                    f |= 1 << d
+            before = int(out[w - 1, s]) if w > 0 else (0 if prev is None else int(prev[s]))
+            f |= ((f & before) & 3) << 2
+            out[w, s] = f
+    return out
 
 
 def rate_bps(nbytes, dur_ms) -> np.ndarray:

@@ -252,6 +252,40 @@ int orc_classify_aggregate_windows(const orc_registry *r, const uint32_t *laddr,
   return ORC_OK;
 }
 
+/*
+ * Per record: its row (the same classification as orc_classify_aggregate),
+ * whether it is a bulk flow (bytes > bulk_bytes and dur > 0) and, if so, its
+ * rate (0 otherwise).  Input of the median statistic: the paper counts each host's
+ * and site's rates in 10 kbps buckets and takes the median of the counts
+ * (§III.B.2, TransRate Kernel; §III.B.1, NetPerf Monitoring Thread).
+ */
+int orc_classify_rows(const orc_registry *r, const uint32_t *laddr, const uint32_t *llen, uint32_t n_local,
+                      const uint32_t *src, const uint32_t *dst, const uint64_t *bytes,
+                      const uint32_t *first_ms, const uint32_t *last_ms, uint64_t n, uint64_t bulk_bytes,
+                      uint32_t *row_out, uint8_t *bulk_out, uint64_t *rate_out) {
+  const uint32_t S = r->n_sites;
+  for (uint32_t j = 0; j < n_local; ++j)
+    if (llen[j] > 32) return ORC_E_INVAL;
+#pragma omp parallel for schedule(static)
+  for (uint64_t i = 0; i < n; ++i) {
+    int ls = orc_is_local(laddr, llen, n_local, src[i]);
+    int ld = orc_is_local(laddr, llen, n_local, dst[i]);
+    uint32_t row;
+    if (ls == ld) {
+      row = 2u * S + 2u;
+    } else {
+      uint32_t remote = ld ? src[i] : dst[i];
+      row = 2u * orc_lookup(r, remote) + (ld ? 0u : 1u);
+    }
+    uint32_t dur = last_ms[i] - first_ms[i];
+    row_out[i] = row;
+    int bulk = bytes[i] > bulk_bytes && dur > 0u;
+    bulk_out[i] = (uint8_t)bulk;
+    rate_out[i] = bulk ? orc_rate_bps(bytes[i], dur) : 0u;
+  }
+  return ORC_OK;
+}
+
 /* Vectorised lookups for tests: site of the longest containing prefix. */
 void orc_lookup_many(const orc_registry *r, const uint32_t *ip, uint64_t n, uint32_t *site_out) {
 #pragma omp parallel for schedule(static)

@@ -6,6 +6,8 @@ brute-force longest-prefix match at every interval boundary, brute-force
 aggregation of random small windows full of edge cases, and conservation /
 permutation / split-merge invariants on generated windows.
 """
+import statistics
+
 import numpy as np
 import pytest
 
@@ -290,3 +292,115 @@ def test_generator_is_deterministic():
         assert (getattr(a, f) == getattr(b, f)).all()
     c = flowgen.records_for(flowgen.PLAIN_SMALL, n=5000, stream=1)
     assert not (a.src_ip == c.src_ip).all()
+
+
+# ---------------------------------------------------------------- median statistic (§III.B.2, §IV.B)
+
+@pytest.mark.parametrize("rate,bucket", [
+    (0, 0), (9_999, 0), (10_000, 1), (999_999, 99), (1_000_000, 100), (99_999_999, 9_999),
+    (100_000_000, 10_000), (100_009_999, 10_000), (100_010_000, 10_000), (M64, 10_000)])
+def test_rate_bucket_closed_forms(rate, bucket):
+    # 10 kbps per bucket; everything past 100 Mbps shares the last of 10,001 buckets
+    assert int(oracle.rate_bucket(np.array([rate], dtype=np.uint64))[0]) == bucket
+
+
+def _brute_buckets(sites, local, n_sites, recs, bulk_bytes):
+    """{row: [bucket of each bulk flow]} by brute force: one record at a time."""
+    out = {}
+    for src, dst, b, _p, f, l in recs:
+        dur = (l - f) & 0xFFFFFFFF
+        if b > bulk_bytes and dur > 0:
+            row = brute.row_of(sites, local, n_sites, src, dst)
+            out.setdefault(row, []).append(min(brute.rate_bps(b, dur) // 10_000, 10_000))
+    return out
+
+
+def _rate_records(rng, n, sites, local):
+    """Bulk-heavy records whose rates cluster near bucket edges and near 1 Mbps."""
+    recs = _edge_records(rng, n, sites, local)
+    out = []
+    for src, dst, b, p, f, l in recs:
+        if rng.random() < 0.5:
+            dur = int(rng.integers(1, 100_000))
+            target = int(rng.choice([999_999, 1_000_000, 10_000 * int(rng.integers(0, 10_002)),
+                                     int(rng.integers(0, 1 << 30))]))
+            b = max(1_000_001, -(-target * dur // 8000) + int(rng.integers(-2, 3)))
+            l = (f + dur) & 0xFFFFFFFF
+        out.append((src, dst, b, p, f, l))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_medians_match_brute_force(seed):
+    rng = np.random.default_rng(700 + seed)
+    n_sites, sites, local = random_tiny_registry(rng, n_local=int(rng.integers(1, 4)))
+    recs = _rate_records(rng, int(rng.integers(0, 200)), sites, local)
+    bulk = int(rng.choice([0, 1_000_000]))
+    cuts = sorted(int(c) for c in rng.integers(0, len(recs) + 1, size=int(rng.integers(0, 4))))
+    off = np.array([0] + cuts + [len(recs)], dtype=np.uint64)
+    reg = _oracle_reg(sites, local, n_sites)
+    med, cnt = oracle.rate_medians(reg, soa(recs), window_offsets=off, bulk_bytes=bulk)
+    hist = oracle.rate_histograms(reg, soa(recs), window_offsets=off, bulk_bytes=bulk)
+    rows = 2 * n_sites + 3
+    assert med.shape == cnt.shape == (len(off) - 1, rows) and hist.shape == (len(off) - 1, rows, 10001)
+    for w in range(len(off) - 1):
+        exp = _brute_buckets(sites, local, n_sites, recs[int(off[w]):int(off[w + 1])], bulk)
+        for r in range(rows):
+            b = exp.get(r, [])
+            assert int(cnt[w, r]) == len(b)
+            assert int(med[w, r]) == (statistics.median_low(b) if b else oracle.NO_MEDIAN)
+            assert np.array_equal(hist[w, r], np.bincount(np.array(b, dtype=np.int64), minlength=10001))
+
+
+def test_median_is_bucket_of_median_rate_on_generated_window():
+    reg = flowgen.registry_for(flowgen.PLAIN_SMALL)
+    rec = flowgen.records_for(flowgen.PLAIN_SMALL, reg=reg, n=20_000)
+    o = oracle.Registry.from_generated(reg)
+    med, cnt = oracle.rate_medians(o, rec)
+    rows = o.classify_aggregate(rec)
+    sites = list(zip(reg.addr.tolist(), reg.length.tolist(), reg.site.tolist()))
+    local = list(zip(reg.local_addr.tolist(), reg.local_len.tolist()))
+    rates = {}
+    for src, dst, b, _p, f, l in tuples(rec):
+        dur = (l - f) & 0xFFFFFFFF
+        if b > 1_000_000 and dur > 0:
+            rates.setdefault(brute.row_of(sites, local, reg.n_sites, src, dst), []).append(brute.rate_bps(b, dur))
+    assert cnt[0].tolist() == rows[:, 4].tolist()  # bulk flows, as the aggregate counts them
+    for r in range(o.rows):
+        if r in rates:
+            assert int(med[0, r]) == min(statistics.median_low(rates[r]) // 10_000, 10_000)
+            assert int(oracle.rate_bucket(rows[r, 6:7])[0]) <= med[0, r] <= int(oracle.rate_bucket(rows[r, 7:8])[0])
+        else:
+            assert med[0, r] == oracle.NO_MEDIAN
+    assert len(rates) > 20
+
+
+def _mf(meds, cnts, **kw):
+    med = np.array(meds, dtype=np.uint32)
+    cnt = np.array(cnts, dtype=np.uint64)
+    return oracle.median_flags(med, cnt, med.shape[1] // 2, **kw).tolist()
+
+
+def test_median_flag_threshold_boundary():
+    # bucket 99 covers [990,000, 1,000,000): its flows are all below 1 Mbps; bucket 100 starts at 1 Mbps
+    assert _mf([[99, 100]], [[1, 1]]) == [[1]]
+    assert _mf([[100, 99]], [[1, 1]]) == [[2]]
+    assert _mf([[0, 10_000]], [[5, 5]], threshold_bps=100_000_000) == [[1]]
+    assert _mf([[0, 0]], [[1, 1]], threshold_bps=0) == [[0]]
+    # no bulk flow, or fewer than the minimum: no median to judge
+    assert _mf([[oracle.NO_MEDIAN, 0]], [[0, 1]]) == [[2]]
+    assert _mf([[0, 0]], [[2, 3]], min_bulk_flows=3) == [[2]]
+    assert _mf([[0, 0]], [[1, 1]], min_bulk_flows=0) == [[3]]
+
+
+def test_median_flag_two_consecutive_windows():
+    # one site; windows: low IN, low IN+OUT, low OUT, nothing, low IN
+    meds = [[0, 500], [0, 0], [500, 0], [500, 500], [0, 500]]
+    cnts = [[1, 1]] * 5
+    assert [f[0] for f in _mf(meds, cnts)] == [1, 3 | 4, 2 | 8, 0, 1]
+    # the window before the first comes from the caller
+    assert [f[0] for f in _mf(meds, cnts, prev=np.array([1], dtype=np.uint8))] == [1 | 4, 3 | 4, 2 | 8, 0, 1]
+    assert [f[0] for f in _mf(meds, cnts, prev=np.array([2 | 8], dtype=np.uint8))] == [1, 3 | 4, 2 | 8, 0, 1]
+    # sites are judged independently
+    two = _mf([[0, 500, 500, 0], [0, 500, 500, 0]], [[1, 1, 1, 1]] * 2)
+    assert two == [[1, 2], [1 | 4, 2 | 8]]
