@@ -105,7 +105,19 @@ typedef struct {
   uint64_t rate_max_bps;
 } gnm_acc;
 
-#define GNM_ACCUMULATE 0x1u /* gnm_params.flags: add into acc instead of initialising it */
+#define GNM_ACCUMULATE 0x1u /* gnm_params.flags: add into acc (and rate_hist) instead of initialising them */
+
+/* Rate histograms (§III.B.2, TransRate Kernel: per-rate frequency counts in
+ * 10 kbps buckets, everything above 100 Mbps in the last of 10,001 buckets,
+ * from which the median is read).  One histogram per registered (site,
+ * direction) row 2*site+dir, site < n_sites, per window: uint32
+ * rate_hist[n_windows][2*n_sites][GNM_RATE_BUCKETS], window-major.  A bulk
+ * flow of rate r counts in bucket min(floor(r / 10,000), 10,000).  Counts
+ * wrap modulo 2^32 (medians are exact while every row of a window has fewer
+ * than 2^32 bulk flows).  The "no site" and NODIR rows have no histogram. */
+#define GNM_RATE_BUCKETS 10001u
+#define GNM_RATE_BUCKET_BPS 10000u
+#define GNM_NO_MEDIAN 0xFFFFFFFFu /* median bucket of a row without bulk flows */
 
 /* Per-call parameters.  Zero-initialise and set what you need;
  * gnm_params_default() gives bulk_bytes = 1,000,000 and automatic tuning. */
@@ -117,6 +129,8 @@ typedef struct {
   uint32_t reserved;
   void *workspace;             /* optional DEVICE scratch, 16-byte aligned; see below */
   uint64_t workspace_bytes;    /* its size; >= gnm_workspace_bytes(reg, grid_blocks) to be used */
+  uint32_t *rate_hist;         /* optional DEVICE rate histograms (layout above), 16-byte aligned: NULL = none;
+                                  else filled by the same pass (zeroed first unless GNM_ACCUMULATE) */
 } gnm_params;
 
 #define GNM_REG_HOST_ONLY 0x1u   /* gnm_registry_opts.flags: build host structure only */
@@ -235,14 +249,17 @@ uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks);
  *                   window-major.  Initialised by the call unless
  *                   p->flags has GNM_ACCUMULATE (then added into).
  *   stream          the caller's stream.
- * Enqueues up to three kernels: table initialisation (skipped when
+ * Enqueues up to four kernels: table initialisation (skipped when
  * accumulating, or when a single window is rebuilt entirely by the reduce
- * step), the classify kernel, and (with a usable p->workspace) the reduce
- * kernel.  Each classify workgroup walks a balanced contiguous slice of all
+ * step), histogram zeroing (p->rate_hist set and not accumulating), the
+ * classify kernel, and (with a usable p->workspace) the reduce kernel.  With
+ * p->rate_hist, each bulk flow of a registered site also adds one to its
+ * row's histogram with a device-scope 32-bit atomic; the caller owns the
+ * histogram memory (n_windows * 2 * n_sites * GNM_RATE_BUCKETS * 4 bytes).  Each classify workgroup walks a balanced contiguous slice of all
  * records, flushing its LDS table at window changes.  Errors: GNM_E_INVAL
  * (null pointers, n_windows = 0, offsets NULL with n_windows > 1,
- * records_per_thread not 0/1/2/4, n_windows tables beyond 2^39 words),
- * GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
+ * records_per_thread not 0/1/2/4, n_windows tables beyond 2^39 words,
+ * rate_hist not 16-byte aligned), GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
  */
 int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
                            const uint64_t *window_offsets, uint32_t n_windows,
@@ -266,6 +283,40 @@ int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_
                         uint64_t threshold_bps, uint64_t min_bulk_flows, uint8_t *flags,
                         hipStream_t stream);
 
+/*
+ * gnm_median_flags — the paper's warning criterion (§III.B.1, NetPerf
+ * Monitoring Thread; §IV.B): a site is warned about when the median of its
+ * transfer rates stays below a standard (1 Mbps) for two consecutive windows
+ * (the paper's hours).
+ *   rate_hist       DEVICE histograms of n_windows windows, as filled by
+ *                   gnm_classify_aggregate with p->rate_hist.
+ *   threshold_bps   e.g. 1,000,000.
+ *   min_bulk_flows  a (site, direction) needs at least max(1, min_bulk_flows)
+ *                   bulk flows (its histogram's total) to be judged.
+ *   prev_flags      NULL, or a DEVICE array of n_sites flag bytes of the
+ *                   window just before the first one (bits 0/1 are read), so
+ *                   that consecutive calls chain across their boundary.
+ *   median_bucket   NULL, or a DEVICE array of n_windows * 2 * n_sites uint32,
+ *                   window-major by row 2*site+dir: the lower median bucket,
+ *                   i.e. the smallest bucket m whose cumulative count reaches
+ *                   ceil(N/2) of the row's N bulk flows; GNM_NO_MEDIAN when
+ *                   N = 0.  The median rate lies in [m * 10 kbps, (m+1) *
+ *                   10 kbps), or above 100 Mbps for the last bucket.
+ *   flags           DEVICE array of n_windows * n_sites bytes, window-major:
+ *                   bit d (0 inbound, 1 outbound) = the row is judged and
+ *                   m * 10,000 < threshold_bps (exactly "median below the
+ *                   threshold" when the threshold is a multiple of 10 kbps);
+ *                   bit 2 + d = bit d is set in this window and in the one
+ *                   before it (the warning).
+ * Enqueues two kernels: the medians and low bits (one workgroup per
+ * (window, site), reading each histogram once), then the two-window rule
+ * (one lane per site).  Errors: GNM_E_INVAL (null pointers, n_windows = 0),
+ * GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP.
+ */
+int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hist, uint32_t n_windows,
+                     uint64_t threshold_bps, uint64_t min_bulk_flows, const uint8_t *prev_flags,
+                     uint32_t *median_bucket, uint8_t *flags, hipStream_t stream);
+
 /* ------------------------------------------------------------------ batched form
  * Many windows of uneven size go through one persistent classify launch (see
  * gnm_classify_aggregate with window offsets); the paper instead launches once
@@ -279,7 +330,8 @@ typedef struct gnm_graph gnm_graph; /* opaque */
  * gnm_graph_create — capture one step: gnm_classify_aggregate(reg, rec,
  * window_offsets, n_windows, p, acc) followed, when flags is not NULL, by
  * gnm_flag_suboptimal(reg, acc, n_windows, threshold_bps, min_bulk_flows,
- * flags).  All pointers (records, offsets, acc, flags, p->workspace) are
+ * flags).  All pointers (records, offsets, acc, flags, p->workspace,
+ * p->rate_hist) are
  * baked into the graph: every replay reads and writes those same buffers,
  * whose contents the caller may change between replays.  The call runs the
  * step once eagerly (results valid on return) and synchronises its own

@@ -37,9 +37,12 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
            "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_classify_aggregate",
-           "gnm_flag_suboptimal", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
+           "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
            "gnm_strerror", "gnm_last_error", "gnm_version")
 TUNE_MAX = 16
+RATE_BUCKETS = 10001        # 10 kbps rate buckets per (site, direction) histogram
+RATE_BUCKET_BPS = 10000
+NO_MEDIAN = 0xFFFFFFFF
 
 
 class Prefix(ctypes.Structure):
@@ -57,7 +60,7 @@ class Params(ctypes.Structure):
     _fields_ = [("bulk_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("records_per_thread", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_uint64)]
+                ("workspace_bytes", ctypes.c_uint64), ("rate_hist", ctypes.c_void_p)]
 
 
 class TuneResult(ctypes.Structure):
@@ -127,6 +130,8 @@ def lib():
         L.gnm_classify_aggregate.restype = ctypes.c_int
         L.gnm_flag_suboptimal.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.gnm_flag_suboptimal.restype = ctypes.c_int
+        L.gnm_median_flags.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P, P, P]
+        L.gnm_median_flags.restype = ctypes.c_int
         L.gnm_graph_create.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32, ctypes.POINTER(Params), P,
                                        ctypes.c_uint64, ctypes.c_uint64, P, ctypes.POINTER(P)]
         L.gnm_graph_create.restype = ctypes.c_int
@@ -255,7 +260,7 @@ def records_struct(rec: Dict[str, "object"], n: Optional[int] = None) -> Records
 
 
 def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_per_thread: int = 0,
-                grid_blocks: int = 0, workspace=None) -> Params:
+                grid_blocks: int = 0, workspace=None, rate_hist=None) -> Params:
     p = lib().gnm_params_default()
     p.bulk_bytes = int(bulk_bytes)
     p.flags = GNM_ACCUMULATE if accumulate else 0
@@ -266,7 +271,23 @@ def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_p
             raise ValueError("workspace must be a contiguous device tensor")
         p.workspace = workspace.data_ptr()
         p.workspace_bytes = workspace.numel() * workspace.element_size()
+    if rate_hist is not None:
+        if not rate_hist.is_cuda or not rate_hist.is_contiguous() or rate_hist.element_size() != 4:
+            raise ValueError("rate_hist must be a contiguous device tensor of 32-bit counts")
+        p.rate_hist = rate_hist.data_ptr()
     return p
+
+
+def rate_hist_words(reg: Registry, n_windows: int = 1) -> int:
+    """Counts in the rate histograms of n_windows windows: n_windows * 2 * n_sites * 10001."""
+    return int(n_windows) * 2 * reg.n_sites * RATE_BUCKETS
+
+
+def make_rate_hist(reg: Registry, n_windows: int = 1, device=None):
+    """A device int32 tensor [n_windows, 2 * n_sites, 10001] for the rate histograms."""
+    import torch
+    return torch.empty((int(n_windows), 2 * reg.n_sites, RATE_BUCKETS), dtype=torch.int32,
+                       device=device if device is not None else "cuda")
 
 
 def workspace_bytes(reg: Registry, grid_blocks: int = 0) -> int:
@@ -284,10 +305,11 @@ def make_workspace(reg: Registry, grid_blocks: int = 0, device=None):
 def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1,
                        bulk_bytes: int = 1_000_000, accumulate: bool = False,
                        records_per_thread: int = 0, grid_blocks: int = 0, stream=None,
-                       n: Optional[int] = None, workspace=None) -> None:
+                       n: Optional[int] = None, workspace=None, rate_hist=None) -> None:
     """gnm_classify_aggregate: acc is a device tensor of n_windows*rows*8 64-bit words.
 
     workspace: optional device tensor from make_workspace() (faster table merge).
+    rate_hist: optional device tensor from make_rate_hist() (bulk-rate histograms).
     """
     c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
     if acc.element_size() * acc.numel() < n_windows * reg.rows * 64 or not acc.is_cuda:
@@ -297,7 +319,9 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
         if window_offsets.element_size() != 8 or window_offsets.numel() < n_windows + 1 or not window_offsets.is_cuda:
             raise ValueError("window_offsets must be a device tensor of n_windows+1 64-bit offsets")
         off = window_offsets.data_ptr()
-    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace)
+    if rate_hist is not None and rate_hist.numel() < rate_hist_words(reg, n_windows):
+        raise ValueError("rate_hist must hold n_windows * 2 * n_sites * 10001 counts")
+    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist)
     _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
                                         ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
                                         _stream_handle(stream)), "gnm_classify_aggregate")
@@ -313,6 +337,36 @@ def flag_suboptimal(reg: Registry, acc, n_windows: int, flags, threshold_bps: in
                                      _stream_handle(stream)), "gnm_flag_suboptimal")
 
 
+def median_flags(reg: Registry, rate_hist, n_windows: int, flags, threshold_bps: int = 1_000_000,
+                 min_bulk_flows: int = 0, prev_flags=None, median_bucket=None, stream=None) -> None:
+    """gnm_median_flags: lower medians of the rate histograms and the two-window warning.
+
+    flags: device uint8 tensor of n_windows*n_sites bytes (bits 0/1 low median,
+    bits 2/3 low in this window and the previous one); prev_flags: optional
+    device uint8 tensor of n_sites bytes for the window before the first;
+    median_bucket: optional device 32-bit tensor of n_windows*2*n_sites buckets.
+    """
+    if not rate_hist.is_cuda or rate_hist.element_size() != 4 or rate_hist.numel() < rate_hist_words(reg, n_windows):
+        raise ValueError("rate_hist must be a device tensor of n_windows * 2 * n_sites * 10001 counts")
+    if flags.element_size() != 1 or flags.numel() < n_windows * reg.n_sites or not flags.is_cuda:
+        raise ValueError("flags must be a device uint8 tensor of n_windows * n_sites bytes")
+    prev = 0
+    if prev_flags is not None:
+        if prev_flags.element_size() != 1 or prev_flags.numel() < reg.n_sites or not prev_flags.is_cuda:
+            raise ValueError("prev_flags must be a device uint8 tensor of n_sites bytes")
+        prev = prev_flags.data_ptr()
+    med = 0
+    if median_bucket is not None:
+        if (median_bucket.element_size() != 4 or median_bucket.numel() < 2 * n_windows * reg.n_sites
+                or not median_bucket.is_cuda):
+            raise ValueError("median_bucket must be a device 32-bit tensor of n_windows * 2 * n_sites entries")
+        med = median_bucket.data_ptr()
+    _check(lib().gnm_median_flags(reg.handle, ctypes.c_void_p(rate_hist.data_ptr()), int(n_windows),
+                                  int(threshold_bps), int(min_bulk_flows), ctypes.c_void_p(prev),
+                                  ctypes.c_void_p(med), ctypes.c_void_p(flags.data_ptr()), _stream_handle(stream)),
+           "gnm_median_flags")
+
+
 class Graph:
     """gnm_graph_create / gnm_graph_launch / gnm_graph_free: one captured step.
 
@@ -321,7 +375,7 @@ class Graph:
 
     def __init__(self, reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1, flags=None,
                  threshold_bps: int = 1_000_000, min_bulk_flows: int = 0, n: Optional[int] = None, **params):
-        self._keep = (reg, rec, acc, window_offsets, flags, params.get("workspace"))
+        self._keep = (reg, rec, acc, window_offsets, flags, params.get("workspace"), params.get("rate_hist"))
         self._rec = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
         self._p = make_params(**params)
         off = 0 if window_offsets is None else window_offsets.data_ptr()

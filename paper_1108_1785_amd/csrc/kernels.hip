@@ -29,6 +29,11 @@
 //     flushed mid-launch at window changes, or when no workspace is given).
 // Several windows go through one persistent launch: workgroups cut the
 // concatenated records into equal slices and flush at window boundaries.
+// On request the same pass also counts every bulk flow of a registered
+// (site, direction) in that row's 10 kbps rate histogram in device memory
+// (the paper's bucket arrays behind its median statistic, §III.B.2), and
+// two small kernels read each histogram's lower median and apply the
+// two-window warning (§III.B.1, §IV.B).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -50,6 +55,11 @@ constexpr uint32_t kThreads = 1024;
 constexpr uint32_t kRedWords = 64;   // reduce kernel: table words per workgroup
 constexpr uint32_t kRedGroups = 16;  // reduce kernel: waves, each summing every 16th slot
 constexpr uint32_t kRedUnroll = 8;   // reduce kernel: slot loads in flight per lane
+constexpr uint32_t kBuckets = 10001;      // rate histogram: 10 kbps buckets, the last for > 100 Mbps
+constexpr uint32_t kBucketBps = 10000;
+constexpr uint32_t kMedThreads = 256;     // median kernel: one workgroup per (window, site)
+constexpr uint32_t kMedChunk = 41;        // buckets summed per lane (odd: LDS reads conflict-free)
+static_assert(kMedThreads * kMedChunk >= kBuckets, "median chunks must cover the histogram");
 
 struct LocalRanges {
   uint32_t n;
@@ -75,6 +85,8 @@ struct ClassifyArgs {
   uint32_t cache_slots;  // LDS cache slots for a table that does not fit in LDS
   u64 *ws;             // NULL: every table is flushed with atomics
   uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
+  uint32_t *hist;      // rate histograms: n_windows * hist_rows * kBuckets counts (HIST variants)
+  uint32_t hist_rows;  // 2 * n_sites: rows of registered sites
   LocalRanges local;
 };
 
@@ -565,9 +577,16 @@ __device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyAr
 }
 
 // Aggregate the tile's classified records.
-template <int R, bool ACC_LDS>
+// Histogram bucket of a rate: floor(rate / 10 kbps), at most the last bucket.
+__device__ __forceinline__ uint32_t rate_bucket(uint64_t rate) {
+  constexpr uint64_t kTop = (uint64_t)kBucketBps * (kBuckets - 1u);  // 100 Mbps
+  return rate >= kTop ? kBuckets - 1u : (uint32_t)rate / kBucketBps;
+}
+
+template <int R, bool ACC_LDS, bool HIST>
 __device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uint32_t (&row)[R], const Rest<R> &r,
-                                               const ClassifyArgs &a, const Lds &L, u64 *g_tab) {
+                                               const ClassifyArgs &a, const Lds &L, u64 *g_tab,
+                                               uint32_t *h_tab) {
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const uint32_t dur = r.l[k] - r.f[k];
@@ -577,16 +596,24 @@ __device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uin
     // (a spare LDS row for invalid records instead of this branch measured
     // 10 % slower on the 64-site registry)
     if (valid[k]) code = accumulate<ACC_LDS>(L, g_tab, row[k], r.b[k], r.pk[k], dur, bulk);
-    if (bulk) add_rate<ACC_LDS>(L, g_tab, code, rate_bps(r.b[k], dur));
+    if (bulk) {
+      const uint64_t rate = rate_bps(r.b[k], dur);
+      add_rate<ACC_LDS>(L, g_tab, code, rate);
+      // count in the row's histogram: registered sites only (not the
+      // "no site" rows or NODIR); device scope, result unused
+      if (HIST && row[k] < a.hist_rows)
+        __hip_atomic_fetch_add(h_tab + (uint64_t)row[k] * kBuckets + rate_bucket(rate), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
-template <int R, bool LINES_LDS, bool ACC_LDS>
+template <int R, bool LINES_LDS, bool ACC_LDS, bool HIST>
 __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r, const ClassifyArgs &a,
-                                             const Lds &L, u64 *g_tab) {
+                                             const Lds &L, u64 *g_tab, uint32_t *h_tab) {
   uint32_t row[R];
   classify_tile<R, LINES_LDS>(t, a, L, row);
-  aggregate_tile<R, ACC_LDS>(t.v, row, r, a, L, g_tab);
+  aggregate_tile<R, ACC_LDS, HIST>(t.v, row, r, a, L, g_tab, h_tab);
 }
 
 // Records [lo, hi) of one window: tiles whose addresses are prefetched one
@@ -594,9 +621,9 @@ __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r,
 // overlaps the locality tests and the trie walk.  (Measured: prefetching the
 // other fields a tile ahead as well, or in the middle of the walk, gained
 // nothing at 4 waves per SIMD.)
-template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS>
-__device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &L, u64 *g_tab, uint64_t lo,
-                                              uint64_t hi) {
+template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS, bool HIST>
+__device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &L, u64 *g_tab, uint32_t *h_tab,
+                                              uint64_t lo, uint64_t hi) {
   constexpr uint64_t T = (uint64_t)kThreads * R;
   Addr<R> cur;
   load_addr<R, VEC>(cur, a, lo, hi);
@@ -607,7 +634,7 @@ __device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &
     load_addr<R, VEC>(nxt, a, base + T, hi);  // past the end: reloads the last records, marked invalid
     uint32_t row[R];
     classify_tile<R, LINES_LDS>(cur, a, L, row);
-    aggregate_tile<R, ACC_LDS>(cur.v, row, rest, a, L, g_tab);
+    aggregate_tile<R, ACC_LDS, HIST>(cur.v, row, rest, a, L, g_tab, h_tab);
     cur = nxt;
   }
 }
@@ -619,7 +646,20 @@ __global__ void init_acc_kernel(u64 *__restrict__ acc, uint64_t words) {
   if (i < words) acc[i] = ((i & 7u) == 6u) ? ~0ull : 0ull;
 }
 
-template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS>
+// Zero n 32-bit words at a 16-byte aligned address: four per lane, grid-stride.
+__global__ void zero_words_kernel(uint32_t *__restrict__ p, uint64_t n) {
+  const uint64_t quads = (n + 3u) / 4u;
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    if (4u * q + 4u <= n) {
+      *(u32x4 *)(p + 4u * q) = u32x4{0u, 0u, 0u, 0u};
+    } else {
+      for (uint64_t j = 4u * q; j < n; ++j) p[j] = 0u;
+    }
+  }
+}
+
+template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS, bool HIST>
 __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint64_t *s_root = (uint64_t *)lds;
@@ -660,6 +700,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     uint64_t seg_end = wend < hi ? wend : hi;
     if (seg_end - i > kMaxRecordsPerFlush) seg_end = i + kMaxRecordsPerFlush;
     u64 *g_tab = a.acc + (uint64_t)w * rows * 8u;
+    uint32_t *h_tab = HIST ? a.hist + (uint64_t)w * a.hist_rows * kBuckets : nullptr;
 
     if (VEC) {
       // whole groups of 4 records with vector loads; up to 3 records before
@@ -671,11 +712,11 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
         Rest<R> mr;
         const bool head = tid < a0 - i, tail = tid >= 3 && tid - 3 < seg_end - a1;
         load_single(m, mr, a, head ? i + tid : a1 + (tid - 3), head || tail);
-        process_tile<R, LINES_LDS, ACC_LDS>(m, mr, a, L, g_tab);
+        process_tile<R, LINES_LDS, ACC_LDS, HIST>(m, mr, a, L, g_tab, h_tab);
       }
-      if (a0 < a1) process_range<4, true, LINES_LDS, ACC_LDS>(a, L, g_tab, a0, a1);
+      if (a0 < a1) process_range<4, true, LINES_LDS, ACC_LDS, HIST>(a, L, g_tab, h_tab, a0, a1);
     } else {
-      process_range<R, false, LINES_LDS, ACC_LDS>(a, L, g_tab, i, seg_end);
+      process_range<R, false, LINES_LDS, ACC_LDS, HIST>(a, L, g_tab, h_tab, i, seg_end);
     }
     if (ACC_LDS) {
       if (seg_end >= hi && a.ws) flush_partial(a, s_acc, w);
@@ -787,6 +828,101 @@ __global__ void flag_kernel(const u64 *__restrict__ acc, uint32_t n_windows, uin
   flags[i] = f;
 }
 
+// Lower medians of the rate histograms, one workgroup per (window, site) item
+// at a time: for each direction d the row's 10,001 counts are staged in LDS,
+// every lane sums a run of 41 consecutive buckets, a block scan gives the
+// runs' cumulative counts, and the lane whose run holds the ceil(N/2)-th
+// smallest of the row's N bulk flows walks it to the bucket.  Writes the
+// buckets (NO_MEDIAN when N = 0) when `median` is not NULL, and bits 0/1 of
+// the item's flag byte: N >= need and bucket * 10 kbps < threshold.
+__global__ __launch_bounds__(kMedThreads) void median_kernel(const uint32_t *__restrict__ hist, uint64_t items,
+                                                             uint64_t threshold, uint64_t need,
+                                                             uint32_t *__restrict__ median,
+                                                             uint8_t *__restrict__ flags) {
+  __shared__ uint32_t h[kMedThreads * kMedChunk];
+  __shared__ u64 wave_sum[kMedThreads / 64];
+  __shared__ uint32_t s_med[2];
+  __shared__ u64 s_total[2];
+  const uint32_t t = threadIdx.x, lane = t % 64u, wave = t / 64u;
+  for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    for (uint32_t d = 0; d < 2; ++d) {
+      const uint32_t *src = hist + (2u * item + d) * kBuckets;  // window-major rows 2s+d
+      __syncthreads();  // the previous row's LDS reads are done
+      for (uint32_t j = t; j < kMedThreads * kMedChunk; j += kMedThreads)
+        h[j] = j < kBuckets ? __builtin_nontemporal_load(src + j) : 0u;
+      __syncthreads();
+      const uint32_t *run = h + t * kMedChunk;
+      u64 s = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < kMedChunk; ++j) s += run[j];
+      u64 incl = s;  // inclusive scan within the wave
+#pragma unroll
+      for (uint32_t o = 1; o < 64; o <<= 1) {
+        const u64 y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      if (lane == 63u) wave_sum[wave] = incl;
+      __syncthreads();
+      u64 total = 0;
+#pragma unroll
+      for (uint32_t v = 0; v < kMedThreads / 64; ++v) {
+        if (v < wave) incl += wave_sum[v];
+        total += wave_sum[v];
+      }
+      const u64 target = total - total / 2u;  // ceil(N / 2)
+      const u64 excl = incl - s;
+      if (t == 0u) {
+        s_total[d] = total;
+        if (total == 0u) s_med[d] = 0xFFFFFFFFu;
+      }
+      if (total != 0u && excl < target && target <= incl) {  // exactly one lane
+        u64 c = excl;
+        uint32_t m = 0;
+        for (uint32_t j = 0; j < kMedChunk; ++j) {
+          c += run[j];
+          if (c >= target) { m = t * kMedChunk + j; break; }
+        }
+        s_med[d] = m;
+      }
+    }
+    __syncthreads();
+    if (t == 0u) {
+      uint8_t f = 0;
+      for (uint32_t d = 0; d < 2; ++d) {
+        const uint32_t m = s_med[d];
+        if (median) median[2u * item + d] = m;
+        if (s_total[d] >= need && (u64)m * kBucketBps < threshold) f |= (uint8_t)(1u << d);
+      }
+      flags[item] = f;
+    }
+  }
+}
+
+// The two-window rule, one lane per site walking the windows in order: bit
+// 2 + d is set when bit d (low median) is set in this window and in the one
+// before it (the caller's `prev` byte for the first window).  Flag bytes are
+// read in independent batches ahead of the rewrites.
+__global__ void warn_kernel(uint8_t *__restrict__ flags, uint32_t n_windows, uint32_t n_sites,
+                            const uint8_t *__restrict__ prev) {
+  constexpr uint32_t kBatch = 32;
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sites) return;
+  uint32_t before = prev ? prev[s] & 3u : 0u;
+  for (uint32_t w0 = 0; w0 < n_windows; w0 += kBatch) {
+    uint32_t low[kBatch];
+#pragma unroll
+    for (uint32_t j = 0; j < kBatch; ++j)
+      low[j] = w0 + j < n_windows ? flags[(uint64_t)(w0 + j) * n_sites + s] & 3u : 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < kBatch; ++j) {
+      if (w0 + j < n_windows) {
+        flags[(uint64_t)(w0 + j) * n_sites + s] = (uint8_t)(low[j] | ((low[j] & before) << 2));
+        before = low[j];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launch plumbing
 
 namespace {
@@ -811,26 +947,31 @@ int device_cus(int dev) {
 
 typedef void (*KernelFn)(const ClassifyArgs);
 
-// variant slot: shape * 4 + lists * 2 + acc; shapes: R=1, R=2, R=4 strided, R=4 vector
-template <int R, bool V>
+// variant slot: hist * 16 + shape * 4 + lists * 2 + acc; shapes: R=1, R=2, R=4 strided, R=4 vector
+template <int R, bool V, bool H>
 KernelFn pick_la(bool lists, bool acc) {
-  if (lists) return acc ? classify_kernel<R, V, true, true> : classify_kernel<R, V, true, false>;
-  return acc ? classify_kernel<R, V, false, true> : classify_kernel<R, V, false, false>;
+  if (lists) return acc ? classify_kernel<R, V, true, true, H> : classify_kernel<R, V, true, false, H>;
+  return acc ? classify_kernel<R, V, false, true, H> : classify_kernel<R, V, false, false, H>;
 }
 
-KernelFn pick(int shape, bool lists, bool acc) {
+template <bool H>
+KernelFn pick_shape(int shape, bool lists, bool acc) {
   switch (shape) {
-    case 0: return pick_la<1, false>(lists, acc);
-    case 1: return pick_la<2, false>(lists, acc);
-    case 2: return pick_la<4, false>(lists, acc);
-    default: return pick_la<4, true>(lists, acc);
+    case 0: return pick_la<1, false, H>(lists, acc);
+    case 1: return pick_la<2, false, H>(lists, acc);
+    case 2: return pick_la<4, false, H>(lists, acc);
+    default: return pick_la<4, true, H>(lists, acc);
   }
+}
+
+KernelFn pick(int shape, bool lists, bool acc, bool hist) {
+  return hist ? pick_shape<true>(shape, lists, acc) : pick_shape<false>(shape, lists, acc);
 }
 
 // Allow every kernel variant the full 160 KB of LDS, once per device.
 hipError_t allow_lds(KernelFn fn, int slot, int dev) {
   static std::mutex mu;
-  static bool done[64][16] = {};
+  static bool done[64][32] = {};
   std::lock_guard<std::mutex> g(mu);
   if (dev >= 0 && dev < 64 && done[dev][slot]) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
@@ -894,6 +1035,11 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     set_last_error("accumulator tables too large");
     return GNM_E_INVAL;
   }
+  const uint64_t hist_words = (uint64_t)n_windows * 2u * reg->n_sites * kBuckets;
+  if (p.rate_hist && !aligned16(p.rate_hist)) {
+    set_last_error("rate_hist must be 16-byte aligned");
+    return GNM_E_INVAL;
+  }
   const uint64_t word_tiles = (kAccFields * rows + kRedWords - 1) / kRedWords;
   const bool use_ws = rec->n > 0 && reg->acc_in_lds && p.workspace &&
                       p.workspace_bytes >= partial_bytes(reg, grid) && aligned16(p.workspace) &&
@@ -911,6 +1057,15 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "init launch");
   }
+  if (p.rate_hist && !(p.flags & GNM_ACCUMULATE)) {
+    const uint64_t quads = (hist_words + 3u) / 4u;
+    const uint64_t cap = (uint64_t)device_cus(dev) * 64u;
+    const uint64_t blocks = (quads + 255u) / 256u < cap ? (quads + 255u) / 256u : cap;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((uint32_t)(blocks ? blocks : 1u)), dim3(256), 0, stream,
+                       p.rate_hist, hist_words);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "histogram init launch");
+  }
   if (rec->n == 0) return GNM_OK;
 
   ClassifyArgs a{};
@@ -922,6 +1077,8 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.root_bits = reg->root_bits; a.node_bits = reg->node_bits; a.n_line_words = (uint32_t)reg->lines.size();
   a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
   a.cache_slots = reg->acc_in_lds ? 0u : reg->cache_slots;
+  a.hist = p.rate_hist;
+  a.hist_rows = 2u * reg->n_sites;
   if (use_ws) {
     a.ws = (u64 *)p.workspace;
     a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);
@@ -935,8 +1092,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   const bool vec = R == 4 && aligned16(rec->src_ip) && aligned16(rec->dst_ip) && aligned16(rec->bytes) &&
                    aligned16(rec->packets) && aligned16(rec->first_ms) && aligned16(rec->last_ms);
   const int shape = vec ? 3 : (R == 1 ? 0 : (R == 2 ? 1 : 2));
-  KernelFn fn = pick(shape, reg->lines_in_lds, reg->acc_in_lds);
-  e = allow_lds(fn, shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0), dev);
+  KernelFn fn = pick(shape, reg->lines_in_lds, reg->acc_in_lds, p.rate_hist != nullptr);
+  e = allow_lds(fn, (p.rate_hist ? 16 : 0) + shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0),
+                dev);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), reg->lds_bytes, stream, a);
   e = hipGetLastError();
@@ -964,5 +1122,28 @@ extern "C" int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, 
                      reg->n_sites, (uint32_t)reg->rows(), threshold_bps, need, flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "flag launch");
+  return GNM_OK;
+}
+
+extern "C" int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hist, uint32_t n_windows,
+                                uint64_t threshold_bps, uint64_t min_bulk_flows, const uint8_t *prev_flags,
+                                uint32_t *median_bucket, uint8_t *flags, hipStream_t stream) {
+  if (!reg || !rate_hist || !flags) { set_last_error("NULL argument"); return GNM_E_INVAL; }
+  if (reg->host_only) { set_last_error("registry was built host-only"); return GNM_E_UNSUPPORTED; }
+  if (n_windows == 0) { set_last_error("n_windows must be >= 1"); return GNM_E_INVAL; }
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const uint64_t items = (uint64_t)n_windows * reg->n_sites;
+  const uint64_t cap = (uint64_t)device_cus(dev) * 8u;
+  const uint64_t need = min_bulk_flows > 1 ? min_bulk_flows : 1;
+  hipLaunchKernelGGL(median_kernel, dim3((uint32_t)(items < cap ? items : cap)), dim3(kMedThreads), 0, stream,
+                     rate_hist, items, threshold_bps, need, median_bucket, flags);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "median launch");
+  hipLaunchKernelGGL(warn_kernel, dim3((reg->n_sites + 255u) / 256u), dim3(256), 0, stream, flags, n_windows,
+                     reg->n_sites, prev_flags);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "warn launch");
   return GNM_OK;
 }
