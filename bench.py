@@ -18,6 +18,9 @@ Beside the headline line, the other forms:
 * large-table: 10 windows of 10 M records against 1,000,000 prefixes /
   20,000 sites (lookup structure and tables beyond LDS), autotuned and
   graph-replayed;
+* median: the same plain and 8-window batched steps with the rate
+  histograms filled by the classify pass, then the lower medians and the
+  two-window warning (the paper's warning criterion);
 * served: open-loop Poisson arrivals (200 windows/s, lognormal sizes with
   median 300 k records, capped at 5 M) through the request loop, host records
   copied in over PCIe; p50/p99 latency from scheduled arrival to result;
@@ -308,6 +311,87 @@ def main():
     parity_notes = {}
     graph_batched_ok = True
 
+    # ---------------------------------------------------------------- median statistic
+    hist_bytes = gnm.rate_hist_words(reg) * 4
+    hist1 = gnm.make_rate_hist(reg, 1, device=dev)
+    med1 = torch.empty(2 * n_sites, dtype=torch.int32, device=dev)
+    mflags1 = torch.empty(n_sites, dtype=torch.uint8, device=dev)
+
+    def median_step(k, ev=None):
+        # classify call with histograms (zeroing + classify + merge), then medians + warning
+        if ev is not None:
+            ev[0].record()
+        gnm.classify_aggregate(reg, structs[k], acc, rate_hist=hist1, **kw)
+        if ev is not None:
+            ev[1].record()
+        gnm.median_flags(reg, hist1, 1, mflags1, median_bucket=med1)
+        if ev is not None:
+            ev[2].record()
+
+    for s in range(args.warmup):
+        median_step(s % args.windows)
+    mev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    tm0 = time.perf_counter()
+    for s in range(args.steps):
+        median_step(s % args.windows, mev[s])
+    torch.cuda.synchronize()
+    wall_m = time.perf_counter() - tm0
+    mk = float(np.mean([a.elapsed_time(b) for a, b, _ in mev]))
+    mm = float(np.mean([b.elapsed_time(c) for _, b, c in mev]))
+    median_step(0)
+    torch.cuda.synchronize()
+    got_m = (hist1.cpu().numpy().view(np.uint32).copy(), med1.cpu().numpy().view(np.uint32).copy(),
+             mflags1.cpu().numpy().copy())
+    log("median (plain): %.3f ms/step; classify+histogram call %.4f ms (plain call %.4f), medians %.4f ms" %
+        (wall_m / args.steps * 1e3, mk, k_avg, mm))
+    hist_b = gnm.make_rate_hist(reg, nb, device=dev)
+    med_b = torch.empty(nb * 2 * n_sites, dtype=torch.int32, device=dev)
+    mflags_b = torch.empty(nb * n_sites, dtype=torch.uint8, device=dev)
+
+    def median_batched(ev=None):
+        if ev is not None:
+            ev[0].record()
+        gnm.classify_aggregate(reg, bstruct, acc_b, window_offsets=off_dev, n_windows=nb, rate_hist=hist_b, **kw)
+        if ev is not None:
+            ev[1].record()
+        gnm.median_flags(reg, hist_b, nb, mflags_b, median_bucket=med_b)
+        if ev is not None:
+            ev[2].record()
+
+    median_batched()
+    mbev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.batched_steps)]
+    torch.cuda.synchronize()
+    tmb0 = time.perf_counter()
+    for s in range(args.batched_steps):
+        median_batched(mbev[s])
+    torch.cuda.synchronize()
+    wall_mb = time.perf_counter() - tmb0
+    mbk = float(np.mean([a.elapsed_time(b) for a, b, _ in mbev]))
+    mbm = float(np.mean([b.elapsed_time(c) for _, b, c in mbev]))
+    got_mb = (hist_b[[0, nb - 1]].cpu().numpy().view(np.uint32).copy(),
+              med_b.cpu().numpy().view(np.uint32).reshape(nb, 2 * n_sites).copy(),
+              mflags_b.cpu().numpy().reshape(nb, n_sites).copy())
+    log("median (batched %d x 10M): %.3f ms/step; classify+histogram call %.4f ms, medians %.4f ms" %
+        (nb, wall_mb / args.batched_steps * 1e3, mbk, mbm))
+    # bytes each step must move at the least: the records' read fields, the
+    # histograms written once (zeroing) and read once (medians)
+    m_alg = n_win * ALG_BYTES_PER_RECORD + 2 * hist_bytes
+    forms["median"] = {
+        "records_per_s": args.steps * n_win / wall_m, "step_ms": wall_m / args.steps * 1e3,
+        "classify_hist_call_ms_avg": mk, "median_call_ms_avg": mm, "plain_call_ms_avg": k_avg,
+        "histogram_overhead": mk / k_avg - 1.0, "hist_bytes_per_window": hist_bytes,
+        "alg_bytes_per_step": m_alg, "step_gb_s": m_alg / ((mk + mm) * 1e-3) / 1e9,
+        "launch": "classify call with rate histograms, then gnm_median_flags (one window per step)"}
+    forms["median_batched"] = {
+        "windows": nb, "records": big.n, "records_per_s": args.batched_steps * big.n / wall_mb,
+        "step_ms": wall_mb / args.batched_steps * 1e3, "classify_hist_call_ms_avg": mbk, "median_call_ms_avg": mbm,
+        "histogram_overhead": mbk / bk - 1.0,
+        "step_gb_s": (big.n * ALG_BYTES_PER_RECORD + 2 * nb * hist_bytes) / ((mbk + mbm) * 1e-3) / 1e9,
+        "launch": "one persistent classify launch with histograms over %d windows, then medians and the "
+                  "two-window warning over them" % nb}
+    del hist_b
+
     if not args.no_forms:
         from paper_1108_1785_amd import serve, tune
         # ------------------------------------------------------------ batched, tuned + graph
@@ -468,6 +552,22 @@ def main():
             bad.append("batched graph")
         if not (got_flags == oracle.flags(exp, n_sites)).all():
             bad.append("flags")
+        # median statistic: window 0 in full, the batched windows' medians and warnings
+        S2 = 2 * n_sites
+        mh = oracle.rate_histograms(orc, parts[0])[:, :S2]
+        mmed, mcnt = oracle.rate_medians(orc, parts[0])
+        if not (got_m[0] == mh).all():
+            bad.append("median histogram")
+        if not (got_m[1] == mmed[0, :S2]).all() or not (got_m[2] == oracle.median_flags(mmed, mcnt, n_sites)[0]).all():
+            bad.append("median / warning")
+        bmed, bcnt = oracle.rate_medians(orc, big)
+        if not (got_mb[1] == bmed[:, :S2]).all() or not (got_mb[2] == oracle.median_flags(bmed, bcnt, n_sites)).all():
+            bad.append("batched medians / warnings")
+        if not (got_mb[0][0] == mh[0]).all() or \
+                not (got_mb[0][1] == oracle.rate_histograms(orc, parts[nb - 1])[0, :S2]).all():
+            bad.append("batched histograms")
+        parity_notes["median_windows_checked"] = "histograms of windows 0 and %d; medians and warnings of all %d" % (
+            nb - 1, nb)
         if not args.no_forms:
             orc1 = oracle.Registry.from_generated(reg1_h)
             rs = np.random.default_rng(5)

@@ -57,9 +57,15 @@ constexpr uint32_t kRedGroups = 16;  // reduce kernel: waves, each summing every
 constexpr uint32_t kRedUnroll = 8;   // reduce kernel: slot loads in flight per lane
 constexpr uint32_t kBuckets = 10001;      // rate histogram: 10 kbps buckets, the last for > 100 Mbps
 constexpr uint32_t kBucketBps = 10000;
-constexpr uint32_t kMedThreads = 256;     // median kernel: one workgroup per (window, site)
-constexpr uint32_t kMedChunk = 41;        // buckets summed per lane (odd: LDS reads conflict-free)
-static_assert(kMedThreads * kMedChunk >= kBuckets, "median chunks must cover the histogram");
+constexpr uint32_t kHistKeyBits = 14;     // LDS histogram cache key: row << 14 | bucket
+constexpr uint32_t kHistSlotsMax = 4096;  // LDS histogram cache slots (8 bytes each, 4-way sets)
+constexpr uint32_t kMedWaves = 4;         // median kernel: one wave per (window, site), 4 per workgroup
+constexpr uint32_t kMedRun = 16;          // buckets per lane per batch: 64 * 16 = 1024 per batch
+constexpr uint32_t kMedBatchWords = 64u * kMedRun;
+constexpr uint32_t kMedBatches = (kBuckets + kMedBatchWords - 1u) / kMedBatchWords;  // 5
+static_assert((1u << kHistKeyBits) > kBuckets, "bucket must fit the key's low bits");
+constexpr uint32_t kMedFullBatches = kBuckets / kMedBatchWords;  // batches with no bucket past the row
+static_assert(kMedBatches <= 64, "batch sums are held one per lane");
 
 struct LocalRanges {
   uint32_t n;
@@ -87,6 +93,7 @@ struct ClassifyArgs {
   uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
   uint32_t *hist;      // rate histograms: n_windows * hist_rows * kBuckets counts (HIST variants)
   uint32_t hist_rows;  // 2 * n_sites: rows of registered sites
+  uint32_t lds_off_hist, hist_slots;  // LDS histogram cache (0 slots: every count goes to device memory)
   LocalRanges local;
 };
 
@@ -300,6 +307,9 @@ struct Lds {
   u64 *acc;        // the accumulator table, or the cache slots' rows
   uint32_t *tags;  // cache slots: row + 1 of the owner, 0 = free
   uint32_t slots;  // cache slots (0 when the table is in LDS)
+  uint32_t *htags;  // histogram cache: key + 1 of the owner, 0 = free
+  uint32_t *hcnt;   // histogram cache: counts
+  uint32_t hslots;  // histogram cache slots (0 = none)
 };
 
 // Staging code of a record whose row lives in an LDS cache slot.
@@ -403,6 +413,49 @@ __device__ __forceinline__ void flush_atomic(u64 *s_acc, u64 *__restrict__ g, ui
     }
     t[kCnt] = t[kBytes] = t[kPackets] = t[kDur] = t[kRateSum] = t[kRateMax] = 0;
     t[kRateMin] = ~0ull;
+  }
+  __syncthreads();
+}
+
+// Count one bulk flow in bucket `bucket` of row `row` of window histogram h.
+// Counts are gathered per workgroup in an LDS cache of (row, bucket) keys
+// with the accumulator cache's discipline (4-way sets, ways claimed in order
+// and kept until the segment ends); a key whose set is full, or a row beyond
+// the key's range, goes to device memory directly.  Device-scope atomics on
+// a few popular buckets serialise in the memory system, so gathering them
+// first matters more than their number.
+__device__ __forceinline__ void hist_add(const Lds &L, uint32_t *h, uint32_t row, uint32_t bucket) {
+  if (L.hslots && row < (1u << (32 - kHistKeyBits)) - 1u) {
+    const uint32_t tag = ((row << kHistKeyBits) | bucket) + 1u;
+    const uint32_t set = cache_set(tag, L.hslots >> 2);
+    uint32_t *tg = L.htags + 4u * set;
+    const u32x4 t4 = *(const u32x4 *)tg;
+    uint32_t w[4] = {t4.x, t4.y, t4.z, t4.w};
+    uint32_t way = 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (way == 4u && w[j] == 0u) w[j] = atomicCAS(&tg[j], 0u, tag) ?: tag;  // claimed, or its owner
+      if (way == 4u && w[j] == tag) way = j;
+    }
+    if (way < 4u) {
+      atomicAdd(&L.hcnt[4u * set + way], 1u);
+      return;
+    }
+  }
+  __hip_atomic_fetch_add(h + (uint64_t)row * kBuckets + bucket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Add the histogram cache into window histogram h and free its slots.
+__device__ __forceinline__ void flush_hist(const Lds &L, uint32_t *h) {
+  __syncthreads();
+  for (uint32_t sl = threadIdx.x; sl < L.hslots; sl += kThreads) {
+    const uint32_t tag = L.htags[sl];
+    if (tag == 0u) continue;
+    const uint32_t key = tag - 1u;
+    __hip_atomic_fetch_add(h + (uint64_t)(key >> kHistKeyBits) * kBuckets + (key & ((1u << kHistKeyBits) - 1u)),
+                           L.hcnt[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    L.htags[sl] = 0u;
+    L.hcnt[sl] = 0u;
   }
   __syncthreads();
 }
@@ -600,10 +653,8 @@ __device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uin
       const uint64_t rate = rate_bps(r.b[k], dur);
       add_rate<ACC_LDS>(L, g_tab, code, rate);
       // count in the row's histogram: registered sites only (not the
-      // "no site" rows or NODIR); device scope, result unused
-      if (HIST && row[k] < a.hist_rows)
-        __hip_atomic_fetch_add(h_tab + (uint64_t)row[k] * kBuckets + rate_bucket(rate), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+      // "no site" rows or NODIR)
+      if (HIST && row[k] < a.hist_rows) hist_add(L, h_tab, row[k], rate_bucket(rate));
     }
   }
 }
@@ -679,8 +730,11 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   const uint32_t acc_words = kAccFields * (ACC_LDS ? rows : slots);
   for (uint32_t i = tid; i < acc_words; i += kThreads) s_acc[i] = (i % kAccFields == kRateMin) ? ~0ull : 0ull;
   for (uint32_t i = tid; i < slots; i += kThreads) s_tags[i] = 0u;
+  const uint32_t hslots = HIST ? a.hist_slots : 0u;
+  uint32_t *s_htags = (uint32_t *)(lds + a.lds_off_hist);
+  for (uint32_t i = tid; i < 2u * hslots; i += kThreads) s_htags[i] = 0u;  // tags, then counts
   __syncthreads();
-  const Lds L{s_root, s_lines, s_acc, s_tags, slots};
+  const Lds L{s_root, s_lines, s_acc, s_tags, slots, s_htags, s_htags + hslots, hslots};
 
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
@@ -724,6 +778,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     } else if (slots) {
       flush_cache(L, g_tab);
     }
+    if (HIST && hslots) flush_hist(L, h_tab);
     i = seg_end;
   }
 }
@@ -828,71 +883,119 @@ __global__ void flag_kernel(const u64 *__restrict__ acc, uint32_t n_windows, uin
   flags[i] = f;
 }
 
-// Lower medians of the rate histograms, one workgroup per (window, site) item
-// at a time: for each direction d the row's 10,001 counts are staged in LDS,
-// every lane sums a run of 41 consecutive buckets, a block scan gives the
-// runs' cumulative counts, and the lane whose run holds the ceil(N/2)-th
-// smallest of the row's N bulk flows walks it to the bucket.  Writes the
-// buckets (NO_MEDIAN when N = 0) when `median` is not NULL, and bits 0/1 of
-// the item's flag byte: N >= need and bucket * 10 kbps < threshold.
-__global__ __launch_bounds__(kMedThreads) void median_kernel(const uint32_t *__restrict__ hist, uint64_t items,
-                                                             uint64_t threshold, uint64_t need,
-                                                             uint32_t *__restrict__ median,
-                                                             uint8_t *__restrict__ flags) {
-  __shared__ uint32_t h[kMedThreads * kMedChunk];
-  __shared__ u64 wave_sum[kMedThreads / 64];
-  __shared__ uint32_t s_med[2];
-  __shared__ u64 s_total[2];
-  const uint32_t t = threadIdx.x, lane = t % 64u, wave = t / 64u;
-  for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    for (uint32_t d = 0; d < 2; ++d) {
-      const uint32_t *src = hist + (2u * item + d) * kBuckets;  // window-major rows 2s+d
-      __syncthreads();  // the previous row's LDS reads are done
-      for (uint32_t j = t; j < kMedThreads * kMedChunk; j += kMedThreads)
-        h[j] = j < kBuckets ? __builtin_nontemporal_load(src + j) : 0u;
-      __syncthreads();
-      const uint32_t *run = h + t * kMedChunk;
-      u64 s = 0;
+__device__ __forceinline__ u64 wave_sum(u64 x) {
 #pragma unroll
-      for (uint32_t j = 0; j < kMedChunk; ++j) s += run[j];
-      u64 incl = s;  // inclusive scan within the wave
+  for (uint32_t o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ u64 wave_inclusive_scan(u64 x, uint32_t lane) {
 #pragma unroll
-      for (uint32_t o = 1; o < 64; o <<= 1) {
-        const u64 y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-      }
-      if (lane == 63u) wave_sum[wave] = incl;
-      __syncthreads();
-      u64 total = 0;
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const u64 y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Lower-median bucket of one histogram row: the bucket holding the
+// ceil(total/2)-th smallest count.  `bsum` holds, on lane b, the total of
+// batch b (1024 buckets), 0 on lanes past the last batch.  The batch holding
+// the target is found by a scan over the lanes, reloaded as 16 consecutive
+// buckets per lane, and the lane whose run holds the target walks it.
+__device__ __forceinline__ uint32_t row_median(const uint32_t *row, u64 bsum, u64 total, uint32_t lane) {
+  if (total == 0u) return 0xFFFFFFFFu;
+  const u64 target = total - total / 2u;
+  const u64 incl = wave_inclusive_scan(bsum, lane);
+  const uint32_t b = (uint32_t)__ffsll((unsigned long long)__ballot(incl >= target)) - 1u;
+  const u64 before = __shfl(incl - bsum, b, 64);
+  const uint32_t base = b * kMedBatchWords + lane * kMedRun;
+  uint32_t v[kMedRun];
+  u64 s = 0;
 #pragma unroll
-      for (uint32_t v = 0; v < kMedThreads / 64; ++v) {
-        if (v < wave) incl += wave_sum[v];
-        total += wave_sum[v];
-      }
-      const u64 target = total - total / 2u;  // ceil(N / 2)
-      const u64 excl = incl - s;
-      if (t == 0u) {
-        s_total[d] = total;
-        if (total == 0u) s_med[d] = 0xFFFFFFFFu;
-      }
-      if (total != 0u && excl < target && target <= incl) {  // exactly one lane
-        u64 c = excl;
-        uint32_t m = 0;
-        for (uint32_t j = 0; j < kMedChunk; ++j) {
-          c += run[j];
-          if (c >= target) { m = t * kMedChunk + j; break; }
-        }
-        s_med[d] = m;
-      }
+  for (uint32_t j = 0; j < kMedRun; ++j) {
+    v[j] = base + j < kBuckets ? row[base + j] : 0u;
+    s += v[j];
+  }
+  const u64 li = wave_inclusive_scan(s, lane) + before;
+  const uint32_t owner = (uint32_t)__ffsll((unsigned long long)__ballot(li >= target)) - 1u;
+  uint32_t m = 0;
+  if (lane == owner) {
+    u64 c = li - s;
+#pragma unroll
+    for (uint32_t j = 0; j < kMedRun; ++j) {
+      c += v[j];
+      if (c >= target) { m = base + j; break; }
     }
-    __syncthreads();
-    if (t == 0u) {
-      uint8_t f = 0;
-      for (uint32_t d = 0; d < 2; ++d) {
-        const uint32_t m = s_med[d];
-        if (median) median[2u * item + d] = m;
-        if (s_total[d] >= need && (u64)m * kBucketBps < threshold) f |= (uint8_t)(1u << d);
+  }
+  return __shfl(m, owner, 64);
+}
+
+// This lane's part of the totals of batch b of two rows (buckets b*1024 +
+// 64j + lane), streamed with coalesced loads, 32 in flight per lane.  The
+// last, partial batch is read as the row's final 1024 buckets (in bounds,
+// same immediate offsets) and counts only its own buckets.
+__device__ __forceinline__ void batch_sums(const uint32_t *r0, const uint32_t *r1, uint32_t b, uint32_t lane,
+                                           u64 &s0, u64 &s1) {
+  const uint32_t lo = b * kMedBatchWords;
+  const uint32_t start = b < kMedFullBatches ? lo : kBuckets - kMedBatchWords;
+  const uint32_t *p0 = r0 + start + lane, *p1 = r1 + start + lane;
+  uint32_t v0[kMedRun], v1[kMedRun];
+#pragma unroll
+  for (uint32_t j = 0; j < kMedRun; ++j) {
+    v0[j] = __builtin_nontemporal_load(p0 + j * 64u);
+    v1[j] = __builtin_nontemporal_load(p1 + j * 64u);
+  }
+  s0 = 0;
+  s1 = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kMedRun; ++j) {
+    const bool mine = start + j * 64u + lane >= lo;
+    s0 += mine ? v0[j] : 0u;
+    s1 += mine ? v1[j] : 0u;
+  }
+}
+
+// Lower medians of the rate histograms: one wave per (window, site) item, the
+// item's two rows (inbound, outbound) side by side.  A first pass streams
+// both rows once, keeping each 1024-bucket batch's total; the second re-reads
+// only the batch that holds the median.  Writes the median buckets (NO_MEDIAN when a row has no
+// bulk flow) when `median` is not NULL, and bits 0/1 of the item's flag
+// byte: total >= need and bucket * 10 kbps < threshold.
+__global__ __launch_bounds__(64 * kMedWaves) void median_kernel(const uint32_t *__restrict__ hist, uint64_t items,
+                                                               uint64_t threshold, uint64_t need,
+                                                               uint32_t *__restrict__ median,
+                                                               uint8_t *__restrict__ flags) {
+  const uint32_t lane = threadIdx.x % 64u, wave = threadIdx.x / 64u;
+  for (uint64_t item = (uint64_t)blockIdx.x * kMedWaves + wave; item < items;
+       item += (uint64_t)gridDim.x * kMedWaves) {
+    const uint32_t *r0 = hist + 2u * item * kBuckets, *r1 = r0 + kBuckets;
+    u64 bs0 = 0, bs1 = 0, t0 = 0, t1 = 0;
+#pragma unroll 1
+    for (uint32_t b = 0; b < kMedBatches; ++b) {
+      u64 s0, s1;
+      batch_sums(r0, r1, b, lane, s0, s1);
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (lane == b) { bs0 = s0; bs1 = s1; }
+      t0 += s0;
+      t1 += s1;
+    }
+    uint32_t m0 = 0, m1 = 0;
+#pragma unroll 1
+    for (uint32_t d = 0; d < 2; ++d) {
+      const uint32_t m = row_median(d ? r1 : r0, d ? bs1 : bs0, d ? t1 : t0, lane);
+      if (d) m1 = m;
+      else m0 = m;
+    }
+    if (lane == 0u) {
+      if (median) {
+        median[2u * item] = m0;
+        median[2u * item + 1u] = m1;
       }
+      uint8_t f = 0;
+      if (t0 >= need && (u64)m0 * kBucketBps < threshold) f |= 1u;
+      if (t1 >= need && (u64)m1 * kBucketBps < threshold) f |= 2u;
       flags[item] = f;
     }
   }
@@ -1079,6 +1182,19 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.cache_slots = reg->acc_in_lds ? 0u : reg->cache_slots;
   a.hist = p.rate_hist;
   a.hist_rows = 2u * reg->n_sites;
+  uint32_t lds_launch = reg->lds_bytes;
+  if (p.rate_hist) {
+    // the histogram cache takes the LDS the registry leaves free, within the
+    // budget that keeps the registry's workgroups per CU
+    const uint32_t off = (reg->lds_bytes + 15u) & ~15u;
+    const uint32_t budget = reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax;
+    uint32_t hs = budget > off ? (budget - off) / 8u : 0u;
+    hs = (hs < kHistSlotsMax ? hs : kHistSlotsMax) & ~3u;
+    if (hs < 64u) hs = 0;
+    a.lds_off_hist = off;
+    a.hist_slots = hs;
+    lds_launch = off + hs * 8u;
+  }
   if (use_ws) {
     a.ws = (u64 *)p.workspace;
     a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);
@@ -1096,7 +1212,7 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   e = allow_lds(fn, (p.rate_hist ? 16 : 0) + shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0),
                 dev);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
-  hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), reg->lds_bytes, stream, a);
+  hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), lds_launch, stream, a);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
   if (use_ws) {
@@ -1135,9 +1251,10 @@ extern "C" int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hi
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   const uint64_t items = (uint64_t)n_windows * reg->n_sites;
-  const uint64_t cap = (uint64_t)device_cus(dev) * 8u;
+  const uint64_t cap = (uint64_t)device_cus(dev) * 64u;
+  const uint64_t blocks = (items + kMedWaves - 1u) / kMedWaves;
   const uint64_t need = min_bulk_flows > 1 ? min_bulk_flows : 1;
-  hipLaunchKernelGGL(median_kernel, dim3((uint32_t)(items < cap ? items : cap)), dim3(kMedThreads), 0, stream,
+  hipLaunchKernelGGL(median_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(64 * kMedWaves), 0, stream,
                      rate_hist, items, threshold_bps, need, median_bucket, flags);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "median launch");
