@@ -14,7 +14,10 @@
  *     bytes and first/last packet timestamps; per-site statistics are
  *     accumulated with atomic updates (§III.B.2, TransRate Kernel);
  *   - sites whose rate statistic falls below a standard are warned about
- *     (§III.B.1, NetPerf Monitoring Thread; §IV.B).
+ *     (§III.B.1, NetPerf Monitoring Thread; §IV.B): the mean rate per window
+ *     (gnm_flag_suboptimal), or the paper's criterion, the median rate read
+ *     from 10 kbps bucket counts, low in two consecutive windows
+ *     (gnm_params.rate_hist, then gnm_median_flags).
  *
  * Definition computed (bit-exact, integer only).  For each record in a window:
  *   mask(L)      = 0 for L = 0, else the top L bits set.
