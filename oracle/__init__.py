@@ -22,6 +22,11 @@ Median statistic: `rate_histograms` counts each row's bulk-flow rates in
 the lower median; `median_flags` applies the two-window warning.  They are
 pinned against a per-record brute force and `statistics.median_low`, bucket
 closed forms and hand-worked flag sequences.
+
+Exclusion filters (`filters=`, see `BulkRule`): the paper's reverse-ACK and
+administrative-flow exclusions as optional thresholds on rate eligibility,
+pinned against the brute force (which compares the exact rational average
+packet size) and boundary closed forms.
 """
 from __future__ import annotations
 
@@ -72,18 +77,48 @@ def lib():
         L.orc_rate_bps.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
         L.orc_rate_bps.restype = ctypes.c_uint64
         L.orc_rate_many.argtypes = [P, P, ctypes.c_uint64, P]
+        R = ctypes.POINTER(BulkRule)
+        L.orc_is_bulk.argtypes = [R, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_is_bulk.restype = ctypes.c_int
         L.orc_classify_aggregate.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, P,
-                                             ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, P]
+                                             ctypes.c_uint64, R, ctypes.c_int, P]
         L.orc_classify_aggregate.restype = ctypes.c_int
         L.orc_classify_aggregate_windows.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, P, P,
-                                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, P]
+                                                     ctypes.c_uint32, R, ctypes.c_int, P]
         L.orc_classify_aggregate_windows.restype = ctypes.c_int
-        L.orc_classify_rows.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, ctypes.c_uint64, ctypes.c_uint64,
+        L.orc_classify_rows.argtypes = [P, P, P, ctypes.c_uint32, P, P, P, P, P, P, ctypes.c_uint64, R,
                                         P, P, P]
         L.orc_classify_rows.restype = ctypes.c_int
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+class BulkRule(ctypes.Structure):
+    """Rate eligibility: bytes > bulk_bytes, dur > 0, and the two optional
+    exclusion filters of §III.B.2 (0 = off): bytes >= min_avg_packet_bytes *
+    packets (reverse-direction ACK flows), packets >= min_packets and dur >=
+    min_duration_ms (administrative exchanges)."""
+    _fields_ = [("bulk_bytes", ctypes.c_uint64), ("min_avg_packet_bytes", ctypes.c_uint32),
+                ("min_packets", ctypes.c_uint32), ("min_duration_ms", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+FILTER_KEYS = ("min_avg_packet_bytes", "min_packets", "min_duration_ms")
+
+
+def bulk_rule(bulk_bytes: int = 1_000_000, filters: Optional[dict] = None) -> BulkRule:
+    f = dict(filters or {})
+    bad = set(f) - set(FILTER_KEYS)
+    if bad:
+        raise ValueError("unknown filters: %s" % sorted(bad))
+    return BulkRule(int(bulk_bytes), *(int(f.get(k, 0)) for k in FILTER_KEYS), 0)
+
+
+def is_bulk(nbytes: int, packets: int, dur_ms: int, bulk_bytes: int = 1_000_000,
+            filters: Optional[dict] = None) -> bool:
+    r = bulk_rule(bulk_bytes, filters)
+    return bool(lib().orc_is_bulk(ctypes.byref(r), int(nbytes), int(packets), int(dur_ms)))
 
 
 def _p(a: np.ndarray):
@@ -135,8 +170,12 @@ class Registry:
         return out
 
     def classify_aggregate(self, rec, bulk_bytes: int = 1_000_000,
-                           threads: int = 0, window_offsets: Optional[np.ndarray] = None) -> np.ndarray:
-        """Rows for each window: uint64[n_windows, rows, 8] (or [rows, 8] for one window)."""
+                           threads: int = 0, window_offsets: Optional[np.ndarray] = None,
+                           filters: Optional[dict] = None) -> np.ndarray:
+        """Rows for each window: uint64[n_windows, rows, 8] (or [rows, 8] for one window).
+
+        filters: optional exclusion thresholds (see BulkRule)."""
+        rule = bulk_rule(bulk_bytes, filters)
         f = {k: np.ascontiguousarray(getattr(rec, k)) for k in
              ("src_ip", "dst_ip", "bytes", "packets", "first_ms", "last_ms")}
         assert f["bytes"].dtype == np.uint64 and f["src_ip"].dtype == np.uint32
@@ -146,7 +185,7 @@ class Registry:
             rc = lib().orc_classify_aggregate(self._h, _p(self.local_addr), _p(self.local_len),
                                               self.local_addr.shape[0], _p(f["src_ip"]), _p(f["dst_ip"]),
                                               _p(f["bytes"]), _p(f["packets"]), _p(f["first_ms"]),
-                                              _p(f["last_ms"]), f["src_ip"].shape[0], bulk_bytes,
+                                              _p(f["last_ms"]), f["src_ip"].shape[0], ctypes.byref(rule),
                                               threads, _p(out))
         else:
             off = np.ascontiguousarray(off, dtype=np.uint64)
@@ -156,7 +195,7 @@ class Registry:
                                                       self.local_addr.shape[0], _p(f["src_ip"]),
                                                       _p(f["dst_ip"]), _p(f["bytes"]), _p(f["packets"]),
                                                       _p(f["first_ms"]), _p(f["last_ms"]), _p(off), nw,
-                                                      bulk_bytes, threads, _p(out))
+                                                      ctypes.byref(rule), threads, _p(out))
         if rc != OK:
             raise OracleError(rc)
         return out
@@ -174,23 +213,27 @@ def rate_bucket(rate_bps) -> np.ndarray:
     return np.minimum(r // np.uint64(RATE_BUCKET_BPS), np.uint64(RATE_BUCKETS - 1)).astype(np.uint32)
 
 
-def _classify_rows(reg: "Registry", rec, bulk_bytes: int):
-    f = {k: np.ascontiguousarray(getattr(rec, k)) for k in ("src_ip", "dst_ip", "bytes", "first_ms", "last_ms")}
+def _classify_rows(reg: "Registry", rec, bulk_bytes: int, filters: Optional[dict] = None):
+    rule = bulk_rule(bulk_bytes, filters)
+    f = {k: np.ascontiguousarray(getattr(rec, k))
+         for k in ("src_ip", "dst_ip", "bytes", "packets", "first_ms", "last_ms")}
     n = f["src_ip"].shape[0]
     row = np.empty(n, dtype=np.uint32)
     bulk = np.empty(n, dtype=np.uint8)
     rate = np.empty(n, dtype=np.uint64)
     rc = lib().orc_classify_rows(reg._h, _p(reg.local_addr), _p(reg.local_len), reg.local_addr.shape[0],
-                                 _p(f["src_ip"]), _p(f["dst_ip"]), _p(f["bytes"]), _p(f["first_ms"]),
-                                 _p(f["last_ms"]), n, bulk_bytes, _p(row), _p(bulk), _p(rate))
+                                 _p(f["src_ip"]), _p(f["dst_ip"]), _p(f["bytes"]), _p(f["packets"]),
+                                 _p(f["first_ms"]), _p(f["last_ms"]), n, ctypes.byref(rule), _p(row), _p(bulk),
+                                 _p(rate))
     if rc != OK:
         raise OracleError(rc)
     return row, bulk.astype(bool), rate
 
 
-def rate_histograms(reg: "Registry", rec, window_offsets=None, bulk_bytes: int = 1_000_000) -> np.ndarray:
+def rate_histograms(reg: "Registry", rec, window_offsets=None, bulk_bytes: int = 1_000_000,
+                    filters: Optional[dict] = None) -> np.ndarray:
     """Counts of bulk-flow rates per (window, row, 10 kbps bucket): uint32[n_windows, rows, 10001]."""
-    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes)
+    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes, filters)
     off = window_offsets if window_offsets is not None else getattr(rec, "window_offsets", None)
     off = np.array([0, rec.n], dtype=np.uint64) if off is None else np.asarray(off, dtype=np.uint64)
     nw = off.shape[0] - 1
@@ -202,14 +245,15 @@ def rate_histograms(reg: "Registry", rec, window_offsets=None, bulk_bytes: int =
     return out
 
 
-def rate_medians(reg: "Registry", rec, window_offsets=None, bulk_bytes: int = 1_000_000):
+def rate_medians(reg: "Registry", rec, window_offsets=None, bulk_bytes: int = 1_000_000,
+                 filters: Optional[dict] = None):
     """Median bucket and bulk-flow count per (window, row).
 
     The median of a row's N >= 1 bulk flows is the bucket of its ceil(N/2)-th
     smallest rate (the lower median), found by sorting the flows' buckets;
     NO_MEDIAN when N = 0.  Returns (uint32[n_windows, rows], uint64[n_windows, rows]).
     """
-    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes)
+    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes, filters)
     off = window_offsets if window_offsets is not None else getattr(rec, "window_offsets", None)
     off = np.array([0, rec.n], dtype=np.uint64) if off is None else np.asarray(off, dtype=np.uint64)
     nw = off.shape[0] - 1

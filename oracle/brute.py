@@ -11,6 +11,8 @@ prefix wins (reading: full CIDR longest-prefix match over /0../32).
 """
 from __future__ import annotations
 
+from fractions import Fraction
+
 M64 = (1 << 64) - 1
 IN, OUT = 0, 1
 
@@ -69,7 +71,23 @@ def empty_rows(n_sites: int):
     return [[0, 0, 0, 0, 0, 0, M64, 0] for _ in range(2 * n_sites + 3)]
 
 
-def classify_aggregate(prefixes, local, n_sites: int, records, bulk_bytes: int):
+def is_bulk(nbytes: int, packets: int, dur: int, bulk_bytes: int, filters=None) -> bool:
+    """Rate eligibility: more than bulk_bytes bytes over a non-zero duration,
+    and, when given, the exclusion filters of §III.B.2 taken literally: an
+    average packet size nbytes / packets of at least min_avg_packet_bytes
+    (reverse-direction pure-ACK flows have small packets; a flow without
+    packets has no average and is kept), at least min_packets packets and a
+    duration of at least min_duration_ms (administrative exchanges)."""
+    f = filters or {}
+    if not (nbytes > bulk_bytes and dur > 0):
+        return False
+    k = f.get("min_avg_packet_bytes", 0)
+    if packets > 0 and Fraction(nbytes, packets) < k:
+        return False
+    return packets >= f.get("min_packets", 0) and dur >= f.get("min_duration_ms", 0)
+
+
+def classify_aggregate(prefixes, local, n_sites: int, records, bulk_bytes: int, filters=None):
     """records: iterable of (src, dst, bytes, packets, first_ms, last_ms)."""
     prefixes = normalise(prefixes)
     rows = empty_rows(n_sites)
@@ -80,7 +98,7 @@ def classify_aggregate(prefixes, local, n_sites: int, records, bulk_bytes: int):
         r[1] += nbytes
         r[2] += packets
         r[3] += dur
-        if nbytes > bulk_bytes and dur > 0:
+        if is_bulk(nbytes, packets, dur, bulk_bytes, filters):
             rate = rate_bps(nbytes, dur)
             r[4] += 1
             r[5] += rate

@@ -54,6 +54,14 @@ typedef struct {
   uint32_t n_sites;
 } orc_registry;
 
+typedef struct {
+  uint64_t bulk_bytes;
+  uint32_t min_avg_packet_bytes;
+  uint32_t min_packets;
+  uint32_t min_duration_ms;
+  uint32_t reserved;
+} orc_bulk_rule;
+
 typedef struct { uint32_t net, site; } orc_pair;
 
 static int orc_pair_cmp(const void *a, const void *b) {
@@ -154,6 +162,22 @@ uint64_t orc_rate_bps(uint64_t bytes, uint32_t dur_ms) {
   return q > (unsigned __int128)UINT64_MAX ? UINT64_MAX : (uint64_t)q;
 }
 
+/*
+ * Which records are rate-eligible ("bulk flows"; §III.B.2, TransRate Kernel).
+ * The paper leaves out of the rate statistics the reverse-direction flows of
+ * pure ACKs, recognised by their small average packet size, and the short
+ * administrative exchanges with few packets and a short duration; it gives no
+ * thresholds.  Read here as: more than bulk_bytes bytes, a non-zero duration,
+ * an average packet size of at least min_avg_packet_bytes (bytes >=
+ * min_avg_packet_bytes * packets, so a flow of 0 packets passes), at least
+ * min_packets packets and a duration of at least min_duration_ms.  Zero
+ * thresholds switch a filter off.
+ */
+int orc_is_bulk(const orc_bulk_rule *b, uint64_t bytes, uint32_t packets, uint32_t dur) {
+  return bytes > b->bulk_bytes && dur > 0u && bytes >= (uint64_t)b->min_avg_packet_bytes * packets &&
+         packets >= b->min_packets && dur >= b->min_duration_ms;
+}
+
 static void orc_row_init(orc_row *t, uint64_t rows) {
   memset(t, 0, rows * sizeof(orc_row));
   for (uint64_t i = 0; i < rows; ++i) t[i].rate_min = UINT64_MAX;
@@ -171,7 +195,7 @@ int orc_classify_aggregate(const orc_registry *r, const uint32_t *laddr, const u
                            uint32_t n_local, const uint32_t *src, const uint32_t *dst,
                            const uint64_t *bytes, const uint32_t *packets,
                            const uint32_t *first_ms, const uint32_t *last_ms, uint64_t n,
-                           uint64_t bulk_bytes, int n_threads, orc_row *out) {
+                           const orc_bulk_rule *rule, int n_threads, orc_row *out) {
   const uint32_t S = r->n_sites;
   const uint64_t rows = 2ull * S + 3ull;
   const uint64_t nodir = 2ull * S + 2ull;
@@ -206,7 +230,7 @@ int orc_classify_aggregate(const orc_registry *r, const uint32_t *laddr, const u
         o->bytes += bytes[i];
         o->packets += packets[i];
         o->duration_ms += dur;
-        if (bytes[i] > bulk_bytes && dur > 0u) {
+        if (orc_is_bulk(rule, bytes[i], packets[i], dur)) {
           uint64_t rate = orc_rate_bps(bytes[i], dur);
           o->bulk_flows += 1u;
           o->rate_sum += rate;
@@ -239,14 +263,14 @@ int orc_classify_aggregate_windows(const orc_registry *r, const uint32_t *laddr,
                                    const uint64_t *bytes, const uint32_t *packets,
                                    const uint32_t *first_ms, const uint32_t *last_ms,
                                    const uint64_t *off, uint32_t n_windows,
-                                   uint64_t bulk_bytes, int n_threads, orc_row *out) {
+                                   const orc_bulk_rule *rule, int n_threads, orc_row *out) {
   const uint64_t rows = 2ull * r->n_sites + 3ull;
   for (uint32_t w = 0; w < n_windows; ++w) {
     uint64_t lo = off[w], hi = off[w + 1];
     if (hi < lo) return ORC_E_INVAL;
     int rc = orc_classify_aggregate(r, laddr, llen, n_local, src + lo, dst + lo, bytes + lo,
                                     packets + lo, first_ms + lo, last_ms + lo, hi - lo,
-                                    bulk_bytes, n_threads, out + (uint64_t)w * rows);
+                                    rule, n_threads, out + (uint64_t)w * rows);
     if (rc) return rc;
   }
   return ORC_OK;
@@ -254,14 +278,14 @@ int orc_classify_aggregate_windows(const orc_registry *r, const uint32_t *laddr,
 
 /*
  * Per record: its row (the same classification as orc_classify_aggregate),
- * whether it is a bulk flow (bytes > bulk_bytes and dur > 0) and, if so, its
+ * whether it is a bulk flow (orc_is_bulk) and, if so, its
  * rate (0 otherwise).  Input of the median statistic: the paper counts each host's
  * and site's rates in 10 kbps buckets and takes the median of the counts
  * (§III.B.2, TransRate Kernel; §III.B.1, NetPerf Monitoring Thread).
  */
 int orc_classify_rows(const orc_registry *r, const uint32_t *laddr, const uint32_t *llen, uint32_t n_local,
-                      const uint32_t *src, const uint32_t *dst, const uint64_t *bytes,
-                      const uint32_t *first_ms, const uint32_t *last_ms, uint64_t n, uint64_t bulk_bytes,
+                      const uint32_t *src, const uint32_t *dst, const uint64_t *bytes, const uint32_t *packets,
+                      const uint32_t *first_ms, const uint32_t *last_ms, uint64_t n, const orc_bulk_rule *rule,
                       uint32_t *row_out, uint8_t *bulk_out, uint64_t *rate_out) {
   const uint32_t S = r->n_sites;
   for (uint32_t j = 0; j < n_local; ++j)
@@ -279,7 +303,7 @@ int orc_classify_rows(const orc_registry *r, const uint32_t *laddr, const uint32
     }
     uint32_t dur = last_ms[i] - first_ms[i];
     row_out[i] = row;
-    int bulk = bytes[i] > bulk_bytes && dur > 0u;
+    int bulk = orc_is_bulk(rule, bytes[i], packets[i], dur);
     bulk_out[i] = (uint8_t)bulk;
     rate_out[i] = bulk ? orc_rate_bps(bytes[i], dur) : 0u;
   }

@@ -304,12 +304,12 @@ def test_rate_bucket_closed_forms(rate, bucket):
     assert int(oracle.rate_bucket(np.array([rate], dtype=np.uint64))[0]) == bucket
 
 
-def _brute_buckets(sites, local, n_sites, recs, bulk_bytes):
+def _brute_buckets(sites, local, n_sites, recs, bulk_bytes, filters=None):
     """{row: [bucket of each bulk flow]} by brute force: one record at a time."""
     out = {}
-    for src, dst, b, _p, f, l in recs:
+    for src, dst, b, p, f, l in recs:
         dur = (l - f) & 0xFFFFFFFF
-        if b > bulk_bytes and dur > 0:
+        if brute.is_bulk(b, p, dur, bulk_bytes, filters):
             row = brute.row_of(sites, local, n_sites, src, dst)
             out.setdefault(row, []).append(min(brute.rate_bps(b, dur) // 10_000, 10_000))
     return out
@@ -404,3 +404,75 @@ def test_median_flag_two_consecutive_windows():
     # sites are judged independently
     two = _mf([[0, 500, 500, 0], [0, 500, 500, 0]], [[1, 1, 1, 1]] * 2)
     assert two == [[1, 2], [1 | 4, 2 | 8]]
+
+
+# ---------------------------------------------------------------- exclusion filters (§III.B.2)
+
+@pytest.mark.parametrize("b,p,d,filters,exp", [
+    (2_000_000, 10, 5, {}, True),
+    (2_000_000, 10, 5, {"min_avg_packet_bytes": 200_000}, True),      # average exactly the minimum
+    (2_000_000, 11, 5, {"min_avg_packet_bytes": 200_000}, False),     # 181,818.18... B per packet
+    (1_999_999, 10, 5, {"min_avg_packet_bytes": 200_000}, False),
+    (2_000_000, 0, 5, {"min_avg_packet_bytes": 4_000_000_000}, True),  # no packets: no average to judge
+    (M64, 2**32 - 1, 5, {"min_avg_packet_bytes": 2**32 - 1}, True),   # product near 2^64
+    (2_000_000, 4, 5, {"min_packets": 5}, False),
+    (2_000_000, 5, 5, {"min_packets": 5}, True),
+    (2_000_000, 5, 99, {"min_duration_ms": 100}, False),
+    (2_000_000, 5, 100, {"min_duration_ms": 100}, True),
+    (2_000_000, 5, 0, {"min_duration_ms": 0}, False),                 # a zero duration never has a rate
+    (1_000_000, 5, 100, {}, False),                                   # bulk threshold is strict
+])
+def test_bulk_rule_closed_forms(b, p, d, filters, exp):
+    assert brute.is_bulk(b, p, d, 1_000_000, filters) is exp
+    assert oracle.is_bulk(b, p, d, 1_000_000, filters) is exp
+
+
+def _random_filters(rng):
+    f = {}
+    if rng.random() < 0.7:
+        f["min_avg_packet_bytes"] = int(rng.choice([1, 64, 100, 1000, 2**31, 2**32 - 1]))
+    if rng.random() < 0.5:
+        f["min_packets"] = int(rng.choice([1, 2, 10, 2**31]))
+    if rng.random() < 0.5:
+        f["min_duration_ms"] = int(rng.choice([1, 2, 1000, 2**31]))
+    return f
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_filters_match_brute_on_edge_windows(seed):
+    rng = np.random.default_rng(1300 + seed)
+    n_sites, sites, local = random_tiny_registry(rng, n_local=int(rng.integers(1, 4)))
+    recs = _edge_records(rng, int(rng.integers(0, 150)), sites, local)
+    # packet counts spread around typical ACK and data sizes
+    recs = [(s, d, b, int(rng.choice([0, 1, 2, 10, b // 64 + 1, b // 1500 + 1, 2**32 - 1])) & 0xFFFFFFFF, f, l)
+            for s, d, b, _p, f, l in recs]
+    bulk = int(rng.choice([0, 1_000_000]))
+    filters = _random_filters(rng)
+    exp = brute.classify_aggregate(sites, local, n_sites, recs, bulk, filters)
+    reg = _oracle_reg(sites, local, n_sites)
+    got = reg.classify_aggregate(soa(recs), bulk, threads=int(rng.integers(1, 4)), filters=filters)
+    assert got.tolist() == exp
+    med, cnt = oracle.rate_medians(reg, soa(recs), bulk_bytes=bulk, filters=filters)
+    buckets = _brute_buckets(sites, local, n_sites, recs, bulk, filters)
+    for r in range(2 * n_sites + 3):
+        b = buckets.get(r, [])
+        assert int(cnt[0, r]) == len(b) == exp[r][4]
+        assert int(med[0, r]) == (statistics.median_low(b) if b else oracle.NO_MEDIAN)
+
+
+def test_filters_only_remove_rate_eligible_flows():
+    reg = flowgen.registry_for(flowgen.PLAIN_SMALL)
+    rec = flowgen.records_for(flowgen.PLAIN_SMALL, reg=reg, n=100_000)
+    o = oracle.Registry.from_generated(reg)
+    base = o.classify_aggregate(rec)
+    assert (o.classify_aggregate(rec, filters={"min_avg_packet_bytes": 0, "min_packets": 0,
+                                               "min_duration_ms": 0}) == base).all()
+    prev = base
+    for f in ({"min_avg_packet_bytes": 100}, {"min_avg_packet_bytes": 100, "min_packets": 1000},
+              {"min_avg_packet_bytes": 100, "min_packets": 1000, "min_duration_ms": 5000}):
+        got = o.classify_aggregate(rec, filters=f)
+        assert (got[:, :4] == base[:, :4]).all()      # flows, bytes, packets, duration: every record
+        assert (got[:, 4] <= prev[:, 4]).all()        # each added filter keeps a subset
+        assert (got[:, 6] >= prev[:, 6]).all() and (got[:, 7] <= prev[:, 7]).all()
+        assert got[:, 4].sum() < prev[:, 4].sum()     # and removes some on this workload
+        prev = got
