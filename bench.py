@@ -21,6 +21,9 @@ Beside the headline line, the other forms:
 * median: the same plain and 8-window batched steps with the rate
   histograms filled by the classify pass, then the lower medians and the
   two-window warning (the paper's warning criterion);
+* filtered: the plain step with the paper's exclusion filters on (average
+  packet size >= 100 B, >= 1,000 packets, >= 5 s), the thresholds being this
+  benchmark's choice (the paper gives none);
 * served: open-loop Poisson arrivals (200 windows/s, lognormal sizes with
   median 300 k records, capped at 5 M) through the request loop, host records
   copied in over PCIe; p50/p99 latency from scheduled arrival to result;
@@ -392,6 +395,27 @@ def main():
                   "two-window warning over them" % nb}
     del hist_b
 
+    # ---------------------------------------------------------------- exclusion filters
+    filt = {"min_avg_packet_bytes": 100, "min_packets": 1000, "min_duration_ms": 5000}
+    kw_f = dict(kw, filters=filt)
+    for s in range(args.warmup):
+        gnm.classify_aggregate(reg, structs[s % args.windows], acc, **kw_f)
+    fstep = [0]
+
+    def filtered_call():
+        gnm.classify_aggregate(reg, structs[fstep[0] % args.windows], acc, **kw_f)
+        fstep[0] += 1
+
+    wall_f, fms = timed_events(filtered_call, args.steps, torch)
+    fk = float(np.mean(fms))
+    gnm.classify_aggregate(reg, structs[0], acc, **kw_f)
+    torch.cuda.synchronize()
+    got_f = gnm.acc_to_numpy(acc)[0].copy()
+    forms["filtered"] = {"records_per_s": args.steps * n_win / wall_f, "call_ms_avg": fk,
+                         "plain_call_ms_avg": k_avg, "filters": filt,
+                         "kernel_gb_s": n_win * ALG_BYTES_PER_RECORD / (fk * 1e-3) / 1e9}
+    log("filtered (plain window, %s): classify call %.4f ms (plain %.4f)" % (filt, fk, k_avg))
+
     if not args.no_forms:
         from paper_1108_1785_amd import serve, tune
         # ------------------------------------------------------------ batched, tuned + graph
@@ -566,6 +590,9 @@ def main():
         if not (got_mb[0][0] == mh[0]).all() or \
                 not (got_mb[0][1] == oracle.rate_histograms(orc, parts[nb - 1])[0, :S2]).all():
             bad.append("batched histograms")
+        exp_f = orc.classify_aggregate(parts[0], filters=filt)
+        if not (got_f == exp_f).all():
+            bad.append("filtered")
         parity_notes["median_windows_checked"] = "histograms of windows 0 and %d; medians and warnings of all %d" % (
             nb - 1, nb)
         if not args.no_forms:

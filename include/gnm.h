@@ -30,7 +30,8 @@
  *                  address, or n_sites ("no registered site") when none does.
  *   row          = 2*site + direction, or NODIR = 2*n_sites + 2.
  *   dur          = (last_ms - first_ms) mod 2^32.
- *   bulk         = bytes > bulk_bytes and dur > 0.
+ *   bulk         = bytes > bulk_bytes and dur > 0 (and the optional
+ *                  exclusion filters of gnm_params).
  *   rate         = min(floor(bytes * 8000 / dur), 2^64 - 1)   [bit/s, decimal]
  *   row.flows += 1; row.bytes += bytes; row.packets += packets;
  *   row.duration_ms += dur; if bulk: row.bulk_flows += 1,
@@ -134,6 +135,16 @@ typedef struct {
   uint64_t workspace_bytes;    /* its size; >= gnm_workspace_bytes(reg, grid_blocks) to be used */
   uint32_t *rate_hist;         /* optional DEVICE rate histograms (layout above), 16-byte aligned: NULL = none;
                                   else filled by the same pass (zeroed first unless GNM_ACCUMULATE) */
+  /* Exclusion filters (§III.B.2, TransRate Kernel: reverse-direction flows of
+   * pure ACKs, recognised by a small average packet size, and administrative
+   * exchanges of few packets over a short time are left out of the rate
+   * statistics; the paper gives no thresholds).  Each narrows which records
+   * count as bulk flows (bulk_flows, rate fields, histograms); flows, bytes,
+   * packets and duration still count every record.  0 = off. */
+  uint32_t min_avg_packet_bytes; /* bulk only if bytes >= min_avg_packet_bytes * packets (0 packets pass) */
+  uint32_t min_packets;          /* bulk only with packets >= min_packets */
+  uint32_t min_duration_ms;      /* bulk only with dur >= min_duration_ms (dur > 0 is always required) */
+  uint32_t reserved2;
 } gnm_params;
 
 #define GNM_REG_HOST_ONLY 0x1u   /* gnm_registry_opts.flags: build host structure only */

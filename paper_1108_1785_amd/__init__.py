@@ -60,7 +60,12 @@ class Params(ctypes.Structure):
     _fields_ = [("bulk_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("records_per_thread", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_uint64), ("rate_hist", ctypes.c_void_p)]
+                ("workspace_bytes", ctypes.c_uint64), ("rate_hist", ctypes.c_void_p),
+                ("min_avg_packet_bytes", ctypes.c_uint32), ("min_packets", ctypes.c_uint32),
+                ("min_duration_ms", ctypes.c_uint32), ("reserved2", ctypes.c_uint32)]
+
+
+FILTER_KEYS = ("min_avg_packet_bytes", "min_packets", "min_duration_ms")
 
 
 class TuneResult(ctypes.Structure):
@@ -260,7 +265,8 @@ def records_struct(rec: Dict[str, "object"], n: Optional[int] = None) -> Records
 
 
 def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_per_thread: int = 0,
-                grid_blocks: int = 0, workspace=None, rate_hist=None) -> Params:
+                grid_blocks: int = 0, workspace=None, rate_hist=None, filters=None) -> Params:
+    """filters: optional dict of exclusion thresholds (FILTER_KEYS), 0 = off."""
     p = lib().gnm_params_default()
     p.bulk_bytes = int(bulk_bytes)
     p.flags = GNM_ACCUMULATE if accumulate else 0
@@ -275,6 +281,14 @@ def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_p
         if not rate_hist.is_cuda or not rate_hist.is_contiguous() or rate_hist.element_size() != 4:
             raise ValueError("rate_hist must be a contiguous device tensor of 32-bit counts")
         p.rate_hist = rate_hist.data_ptr()
+    f = dict(filters or {})
+    if set(f) - set(FILTER_KEYS):
+        raise ValueError("unknown filters: %s" % sorted(set(f) - set(FILTER_KEYS)))
+    for k in FILTER_KEYS:
+        v = int(f.get(k, 0))
+        if not 0 <= v < 2**32:
+            raise ValueError("%s must fit 32 bits" % k)
+        setattr(p, k, v)
     return p
 
 
@@ -305,11 +319,12 @@ def make_workspace(reg: Registry, grid_blocks: int = 0, device=None):
 def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1,
                        bulk_bytes: int = 1_000_000, accumulate: bool = False,
                        records_per_thread: int = 0, grid_blocks: int = 0, stream=None,
-                       n: Optional[int] = None, workspace=None, rate_hist=None) -> None:
+                       n: Optional[int] = None, workspace=None, rate_hist=None, filters=None) -> None:
     """gnm_classify_aggregate: acc is a device tensor of n_windows*rows*8 64-bit words.
 
     workspace: optional device tensor from make_workspace() (faster table merge).
     rate_hist: optional device tensor from make_rate_hist() (bulk-rate histograms).
+    filters: optional exclusion thresholds, e.g. {"min_avg_packet_bytes": 100}.
     """
     c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
     if acc.element_size() * acc.numel() < n_windows * reg.rows * 64 or not acc.is_cuda:
@@ -321,7 +336,7 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
         off = window_offsets.data_ptr()
     if rate_hist is not None and rate_hist.numel() < rate_hist_words(reg, n_windows):
         raise ValueError("rate_hist must hold n_windows * 2 * n_sites * 10001 counts")
-    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist)
+    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist, filters)
     _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
                                         ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
                                         _stream_handle(stream)), "gnm_classify_aggregate")

@@ -94,6 +94,8 @@ struct ClassifyArgs {
   uint32_t *hist;      // rate histograms: n_windows * hist_rows * kBuckets counts (HIST variants)
   uint32_t hist_rows;  // 2 * n_sites: rows of registered sites
   uint32_t lds_off_hist, hist_slots;  // LDS histogram cache (0 slots: every count goes to device memory)
+  uint32_t filters;                   // any exclusion filter set
+  uint32_t min_avg_packet_bytes, min_packets, min_duration_ms;
   LocalRanges local;
 };
 
@@ -644,7 +646,12 @@ __device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uin
   for (int k = 0; k < R; ++k) {
     const uint32_t dur = r.l[k] - r.f[k];
     // (bitwise, not short-circuit: no branches)
-    const bool bulk = valid[k] & (r.b[k] > a.bulk_bytes) & (dur != 0u);
+    bool bulk = valid[k] & (r.b[k] > a.bulk_bytes) & (dur != 0u);
+    // exclusion filters: average packet size, packet count, duration (one
+    // wave-uniform branch when none is set)
+    if (a.filters)
+      bulk = bulk & (r.b[k] >= (uint64_t)a.min_avg_packet_bytes * r.pk[k]) & (r.pk[k] >= a.min_packets) &
+             (dur >= a.min_duration_ms);
     uint32_t code = row[k];
     // (a spare LDS row for invalid records instead of this branch measured
     // 10 % slower on the 64-site registry)
@@ -1176,6 +1183,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.first = rec->first_ms; a.last = rec->last_ms; a.n = rec->n;
   a.woff = (gu64 *)window_offsets; a.n_windows = n_windows; a.rows = (uint32_t)rows;
   a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
+  a.min_avg_packet_bytes = p.min_avg_packet_bytes; a.min_packets = p.min_packets;
+  a.min_duration_ms = p.min_duration_ms;
+  a.filters = (p.min_avg_packet_bytes | p.min_packets | p.min_duration_ms) != 0u;
   a.root = (gu64 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
   a.root_bits = reg->root_bits; a.node_bits = reg->node_bits; a.n_line_words = (uint32_t)reg->lines.size();
   a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;

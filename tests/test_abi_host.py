@@ -199,3 +199,14 @@ def test_automatic_first_level_width():
     for wl in (flowgen.PLAIN_LARGE, flowgen.LARGE_TABLE):
         info = gnm.Registry.from_generated(flowgen.registry_for(wl), host_only=True).info()
         assert info["node_bits"] == 12
+
+
+def test_filter_params_checked():
+    p = gnm.make_params(filters={"min_avg_packet_bytes": 100, "min_packets": 2, "min_duration_ms": 3})
+    assert (p.min_avg_packet_bytes, p.min_packets, p.min_duration_ms) == (100, 2, 3)
+    assert gnm.make_params().min_packets == 0
+    with pytest.raises(ValueError):
+        gnm.make_params(filters={"min_packets": 2**32})
+    with pytest.raises(ValueError):
+        gnm.make_params(filters={"max_packets": 1})
+    assert set(gnm.FILTER_KEYS) == set(oracle.FILTER_KEYS)
