@@ -410,3 +410,130 @@ def permuted(rec: Records, rng) -> Records:
     """Same records in a random order (single window)."""
     perm = rng.permutation(rec.n)
     return Records(*(getattr(rec, f)[perm] for f in Records.FIELDS))
+
+
+# ---------------------------------------------------------------- NetFlow v5 datagrams
+#
+# Export datagrams in the public NetFlow version 5 format, which the paper's
+# routers send (§III.B.1, FlowData Receiver Thread; §IV.A.3: 48-byte records,
+# at most 30 per 1500-byte datagram).  All fields big-endian.  Header, 24 B:
+# version u16 (= 5), count u16 (records that follow, 1..30), sys_uptime u32
+# (ms), unix_secs u32, unix_nsecs u32, flow_sequence u32, engine_type u8,
+# engine_id u8, sampling_interval u16.  Record, 48 B: srcaddr u32, dstaddr
+# u32, nexthop u32, input u16, output u16, dPkts u32, dOctets u32, First u32,
+# Last u32 (sys_uptime at the first and last packet), srcport u16, dstport
+# u16, pad1 u8, tcp_flags u8, prot u8, tos u8, src_as u16, dst_as u16,
+# src_mask u8, dst_mask u8, pad2 u16.
+V5_HEADER = np.dtype([("version", ">u2"), ("count", ">u2"), ("sys_uptime", ">u4"), ("unix_secs", ">u4"),
+                      ("unix_nsecs", ">u4"), ("flow_sequence", ">u4"), ("engine_type", "u1"),
+                      ("engine_id", "u1"), ("sampling_interval", ">u2")])
+V5_RECORD = np.dtype([("srcaddr", ">u4"), ("dstaddr", ">u4"), ("nexthop", ">u4"), ("input", ">u2"),
+                      ("output", ">u2"), ("dPkts", ">u4"), ("dOctets", ">u4"), ("First", ">u4"),
+                      ("Last", ">u4"), ("srcport", ">u2"), ("dstport", ">u2"), ("pad1", "u1"),
+                      ("tcp_flags", "u1"), ("prot", "u1"), ("tos", "u1"), ("src_as", ">u2"),
+                      ("dst_as", ">u2"), ("src_mask", "u1"), ("dst_mask", "u1"), ("pad2", ">u2")])
+assert V5_HEADER.itemsize == 24 and V5_RECORD.itemsize == 48
+V5_MAX_RECORDS = 30
+MALFORMED_KINDS = ("version", "count0", "count31", "truncated", "short", "misaligned")
+
+
+def v5_records(workload: str, n: int, stream: int = 0) -> Records:
+    """Records of a workload's recipe as a router exports them: byte counts fit
+    the 32-bit dOctets field (cap 2^32 - 1)."""
+    reg = registry_for(workload)
+    rng = np.random.Generator(np.random.PCG64([SEED_BASE, _SEED_INDEX[workload], 7, stream]))
+    return make_records(rng, reg, sampler_for(workload, reg), n, bytes_cap=0xFFFFFFFF)
+
+
+def encode_netflow_v5(rec: Records, rng, partial_frac: float = 0.1, malformed: int = 0):
+    """Pack records into back-to-back v5 datagrams (uint8 buffer, uint64 offsets[n+1]).
+
+    Most datagrams carry 30 records, a partial_frac share fewer (routers also
+    flush partly filled datagrams); `malformed` extra datagrams of the
+    MALFORMED_KINDS, which carry none of the records, are mixed in.  Datagram
+    starts are multiples of 4 (a misaligned one is preceded by 2 bytes of
+    padding in its predecessor's span).
+    """
+    if int(rec.bytes.max(initial=0)) > 0xFFFFFFFF:
+        raise ValueError("NetFlow v5 carries 32-bit byte counts")
+    n = rec.n
+    counts = []
+    left = n
+    while left > 0:
+        c = V5_MAX_RECORDS if rng.random() >= partial_frac else int(rng.integers(1, V5_MAX_RECORDS))
+        c = min(c, left)
+        counts.append(c)
+        left -= c
+    bad_kinds = [MALFORMED_KINDS[int(k)] for k in rng.integers(0, len(MALFORMED_KINDS), size=malformed)]
+    bad_at = sorted(int(x) for x in rng.integers(0, len(counts) + 1, size=malformed))
+    items = []  # ("ok", first record, count) or ("bad", kind)
+    first = 0
+    bi = 0
+    for d, c in enumerate(counts + [0]):
+        while bi < len(bad_at) and bad_at[bi] == d:
+            items.append(("bad", bad_kinds[bi]))
+            bi += 1
+        if d < len(counts):
+            items.append(("ok", first, c))
+            first += c
+    parts, offsets, pos, seq = [], [], 0, 0
+    uptime = int(rng.integers(0, 1 << 32))
+    for it in items:
+        if it[0] == "ok":
+            _, lo, c = it
+            h = np.zeros(1, dtype=V5_HEADER)
+            h["version"], h["count"], h["sys_uptime"] = 5, c, uptime
+            h["unix_secs"], h["unix_nsecs"], h["flow_sequence"] = 1_300_000_000 + seq // 1000, seq % 10**9, seq
+            h["engine_type"], h["engine_id"] = 1, 2
+            r = np.zeros(c, dtype=V5_RECORD)
+            s = slice(lo, lo + c)
+            r["srcaddr"], r["dstaddr"] = rec.src_ip[s], rec.dst_ip[s]
+            r["nexthop"] = rng.integers(0, 1 << 32, size=c, dtype=np.uint64).astype(np.uint32)
+            r["input"], r["output"] = rng.integers(0, 64, size=c), rng.integers(0, 64, size=c)
+            r["dPkts"], r["dOctets"] = rec.packets[s], rec.bytes[s].astype(np.uint32)
+            r["First"], r["Last"] = rec.first_ms[s], rec.last_ms[s]
+            r["srcport"], r["dstport"] = rec.src_port[s], rec.dst_port[s]
+            r["tcp_flags"], r["prot"] = rng.integers(0, 256, size=c), rec.proto[s]
+            r["src_as"], r["dst_as"] = rng.integers(0, 1 << 16, size=c), rng.integers(0, 1 << 16, size=c)
+            r["src_mask"], r["dst_mask"] = rng.integers(0, 33, size=c), rng.integers(0, 33, size=c)
+            blob = h.tobytes() + r.tobytes()
+            seq += c
+        else:
+            kind = it[1]
+            c = int(rng.integers(1, V5_MAX_RECORDS + 1))
+            h = np.zeros(1, dtype=V5_HEADER)
+            h["version"], h["count"] = 5, c
+            body = rng.integers(0, 256, size=48 * c, dtype=np.uint8).tobytes()
+            if kind == "version":
+                h["version"] = int(rng.choice([1, 7, 9, 0x0500]))
+                blob = h.tobytes() + body
+            elif kind == "count0":
+                h["count"] = 0
+                blob = h.tobytes()
+            elif kind == "count31":
+                h["count"] = int(rng.choice([31, 0xFFFF]))
+                blob = h.tobytes() + body
+            elif kind == "truncated":
+                # cut by a multiple of 4, so that alignment padding cannot restore it
+                blob = (h.tobytes() + body)[:24 + 48 * c - 4 * int(rng.integers(1, 12))]
+            elif kind == "short":
+                blob = h.tobytes()[:4 * int(rng.integers(0, 6))]
+            else:  # misaligned: a valid datagram starting 2 bytes past a multiple of 4
+                blob = h.tobytes() + body
+        pad = (-len(blob)) % 4
+        if it[0] == "bad" and it[1] == "misaligned":
+            parts.append(b"\0\0")
+            pos += 2
+            offsets.append(pos)
+            parts.append(blob + b"\0\0")  # back to a multiple of 4 after it
+            pos += len(blob) + 2
+            pad = (-pos) % 4
+            parts.append(b"\0" * pad)
+            pos += pad
+            continue
+        offsets.append(pos)
+        parts.append(blob + b"\0" * pad)
+        pos += len(blob) + pad
+    offsets.append(pos)
+    buf = np.frombuffer(b"".join(parts), dtype=np.uint8).copy()
+    return buf, np.array(offsets, dtype=np.uint64)

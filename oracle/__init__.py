@@ -23,6 +23,11 @@ the lower median; `median_flags` applies the two-window warning.  They are
 pinned against a per-record brute force and `statistics.median_low`, bucket
 closed forms and hand-worked flag sequences.
 
+NetFlow v5 decode (`oracle.netflow`): the step before the path, datagrams to
+SoA records, parsed with `struct`; pinned by a hand-built datagram, the
+paper's sizes, a round trip through the generator's numpy encoder and every
+kind of malformed datagram.
+
 Exclusion filters (`filters=`, see `BulkRule`): the paper's reverse-ACK and
 administrative-flow exclusions as optional thresholds on rate eligibility,
 pinned against the brute force (which compares the exact rational average
