@@ -476,62 +476,61 @@ def encode_netflow_v5(rec: Records, rng, partial_frac: float = 0.1, malformed: i
         if d < len(counts):
             items.append(("ok", first, c))
             first += c
-    parts, offsets, pos, seq = [], [], 0, 0
-    uptime = int(rng.integers(0, 1 << 32))
+    # every well-formed datagram's header and all records, serialised once
+    ok = [it for it in items if it[0] == "ok"]
+    hdr = np.zeros(len(ok), dtype=V5_HEADER)
+    cnt = np.array([it[2] for it in ok], dtype=np.int64)
+    seq0 = np.concatenate([[0], np.cumsum(cnt)[:-1]]).astype(np.int64)
+    hdr["version"], hdr["count"] = 5, cnt
+    hdr["sys_uptime"] = int(rng.integers(0, 1 << 32))
+    hdr["unix_secs"], hdr["unix_nsecs"], hdr["flow_sequence"] = 1_300_000_000 + seq0 // 1000, seq0 % 10**9, seq0
+    hdr["engine_type"], hdr["engine_id"] = 1, 2
+    r = np.zeros(n, dtype=V5_RECORD)
+    r["srcaddr"], r["dstaddr"] = rec.src_ip, rec.dst_ip
+    r["nexthop"] = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    r["input"], r["output"] = rng.integers(0, 64, size=n), rng.integers(0, 64, size=n)
+    r["dPkts"], r["dOctets"] = rec.packets, rec.bytes.astype(np.uint32)
+    r["First"], r["Last"] = rec.first_ms, rec.last_ms
+    r["srcport"], r["dstport"] = rec.src_port, rec.dst_port
+    r["tcp_flags"], r["prot"] = rng.integers(0, 256, size=n), rec.proto
+    r["src_as"], r["dst_as"] = rng.integers(0, 1 << 16, size=n), rng.integers(0, 1 << 16, size=n)
+    r["src_mask"], r["dst_mask"] = rng.integers(0, 33, size=n), rng.integers(0, 33, size=n)
+    hb, rb = memoryview(hdr.tobytes()), memoryview(r.tobytes())
+    parts, offsets, pos, k = [], [], 0, 0
     for it in items:
         if it[0] == "ok":
             _, lo, c = it
-            h = np.zeros(1, dtype=V5_HEADER)
-            h["version"], h["count"], h["sys_uptime"] = 5, c, uptime
-            h["unix_secs"], h["unix_nsecs"], h["flow_sequence"] = 1_300_000_000 + seq // 1000, seq % 10**9, seq
-            h["engine_type"], h["engine_id"] = 1, 2
-            r = np.zeros(c, dtype=V5_RECORD)
-            s = slice(lo, lo + c)
-            r["srcaddr"], r["dstaddr"] = rec.src_ip[s], rec.dst_ip[s]
-            r["nexthop"] = rng.integers(0, 1 << 32, size=c, dtype=np.uint64).astype(np.uint32)
-            r["input"], r["output"] = rng.integers(0, 64, size=c), rng.integers(0, 64, size=c)
-            r["dPkts"], r["dOctets"] = rec.packets[s], rec.bytes[s].astype(np.uint32)
-            r["First"], r["Last"] = rec.first_ms[s], rec.last_ms[s]
-            r["srcport"], r["dstport"] = rec.src_port[s], rec.dst_port[s]
-            r["tcp_flags"], r["prot"] = rng.integers(0, 256, size=c), rec.proto[s]
-            r["src_as"], r["dst_as"] = rng.integers(0, 1 << 16, size=c), rng.integers(0, 1 << 16, size=c)
-            r["src_mask"], r["dst_mask"] = rng.integers(0, 33, size=c), rng.integers(0, 33, size=c)
-            blob = h.tobytes() + r.tobytes()
-            seq += c
-        else:
-            kind = it[1]
-            c = int(rng.integers(1, V5_MAX_RECORDS + 1))
-            h = np.zeros(1, dtype=V5_HEADER)
-            h["version"], h["count"] = 5, c
-            body = rng.integers(0, 256, size=48 * c, dtype=np.uint8).tobytes()
-            if kind == "version":
-                h["version"] = int(rng.choice([1, 7, 9, 0x0500]))
-                blob = h.tobytes() + body
-            elif kind == "count0":
-                h["count"] = 0
-                blob = h.tobytes()
-            elif kind == "count31":
-                h["count"] = int(rng.choice([31, 0xFFFF]))
-                blob = h.tobytes() + body
-            elif kind == "truncated":
-                # cut by a multiple of 4, so that alignment padding cannot restore it
-                blob = (h.tobytes() + body)[:24 + 48 * c - 4 * int(rng.integers(1, 12))]
-            elif kind == "short":
-                blob = h.tobytes()[:4 * int(rng.integers(0, 6))]
-            else:  # misaligned: a valid datagram starting 2 bytes past a multiple of 4
-                blob = h.tobytes() + body
-        pad = (-len(blob)) % 4
-        if it[0] == "bad" and it[1] == "misaligned":
+            offsets.append(pos)
+            parts.append(hb[24 * k: 24 * (k + 1)])
+            parts.append(rb[48 * lo: 48 * (lo + c)])
+            pos += 24 + 48 * c  # a multiple of 8: the next start stays aligned
+            k += 1
+            continue
+        kind = it[1]
+        c = int(rng.integers(1, V5_MAX_RECORDS + 1))
+        h = np.zeros(1, dtype=V5_HEADER)
+        h["version"], h["count"] = 5, c
+        body = rng.integers(0, 256, size=48 * c, dtype=np.uint8).tobytes()
+        if kind == "version":
+            h["version"] = int(rng.choice([1, 7, 9, 0x0500]))
+            blob = h.tobytes() + body
+        elif kind == "count0":
+            h["count"] = 0
+            blob = h.tobytes()
+        elif kind == "count31":
+            h["count"] = int(rng.choice([31, 0xFFFF]))
+            blob = h.tobytes() + body
+        elif kind == "truncated":
+            # cut by a multiple of 4, so that alignment padding cannot restore it
+            blob = (h.tobytes() + body)[:24 + 48 * c - 4 * int(rng.integers(1, 12))]
+        elif kind == "short":
+            blob = h.tobytes()[:4 * int(rng.integers(0, 6))]
+        else:  # misaligned: a valid datagram starting 2 bytes past a multiple of 4
             parts.append(b"\0\0")
             pos += 2
-            offsets.append(pos)
-            parts.append(blob + b"\0\0")  # back to a multiple of 4 after it
-            pos += len(blob) + 2
-            pad = (-pos) % 4
-            parts.append(b"\0" * pad)
-            pos += pad
-            continue
+            blob = h.tobytes() + body + b"\0\0"
         offsets.append(pos)
+        pad = (-(pos + len(blob))) % 4
         parts.append(blob + b"\0" * pad)
         pos += len(blob) + pad
     offsets.append(pos)

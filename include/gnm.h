@@ -387,6 +387,64 @@ int gnm_autotune(const gnm_registry *reg, const gnm_records *rec, const uint64_t
                  uint32_t n_windows, const gnm_params *base, gnm_acc *acc, uint32_t reps,
                  hipStream_t stream, gnm_tune_result *out);
 
+/* ------------------------------------------------------------------ NetFlow v5 ingest
+ * The step before the path: router export datagrams (§III.B.1, FlowData
+ * Receiver Thread; §IV.A.3: NetFlow V5, 48-byte records, at most 30 per
+ * datagram) decoded on the device into the structure-of-arrays records that
+ * gnm_classify_aggregate reads.  Field layout: the public NetFlow version 5
+ * export format, every field big-endian; a 24-byte header (version u16,
+ * count u16, sys_uptime, unix_secs, unix_nsecs, flow_sequence u32,
+ * engine_type u8, engine_id u8, sampling_interval u16) and 48-byte records
+ * (srcaddr, dstaddr, nexthop u32, input, output u16, dPkts, dOctets, First,
+ * Last u32, srcport, dstport u16, pad1, tcp_flags, prot, tos u8, src_as,
+ * dst_as u16, src_mask, dst_mask u8, pad2 u16).  Decoded: src_ip = srcaddr,
+ * dst_ip = dstaddr, packets = dPkts, bytes = dOctets (zero-extended),
+ * first_ms = First, last_ms = Last, ports, proto = prot.
+ */
+
+/* Writable SoA record arrays (DEVICE pointers) of `capacity` records. */
+typedef struct {
+  uint32_t *src_ip;
+  uint32_t *dst_ip;
+  uint16_t *src_port; /* may be NULL (not written) */
+  uint16_t *dst_port; /* may be NULL (not written) */
+  uint8_t *proto;     /* may be NULL (not written) */
+  uint64_t *bytes;
+  uint32_t *packets;
+  uint32_t *first_ms;
+  uint32_t *last_ms;
+  uint64_t capacity;
+} gnm_records_out;
+
+/* Scratch bytes gnm_netflow_v5_decode needs for n_datagrams datagrams. */
+uint64_t gnm_netflow_v5_workspace_bytes(uint64_t n_datagrams);
+
+/*
+ * gnm_netflow_v5_decode — decode datagrams stored back to back.
+ *   datagrams       DEVICE buffer of buf_bytes bytes, 4-byte aligned.
+ *   offsets         DEVICE array of n_datagrams+1 uint64: datagram d spans
+ *                   [offsets[d], offsets[d+1]).
+ *   workspace       DEVICE scratch of gnm_netflow_v5_workspace_bytes(n)
+ *                   bytes, 256-byte aligned, caller-owned (contents do not
+ *                   matter; calls in flight must not share one).
+ *   out             output arrays; record j of the accepted datagrams, in
+ *                   datagram order, goes to index j if j < out->capacity
+ *                   (later records are dropped).
+ *   n_records       DEVICE uint64: records the accepted datagrams carry
+ *                   (may exceed out->capacity).
+ *   n_rejected      DEVICE uint64: datagrams rejected.
+ * A datagram is accepted when its span lies in the buffer, starts at a
+ * multiple of 4, holds the header, carries version 5 and a count of 1..30,
+ * and holds count records (bytes after them are ignored).  Enqueues five
+ * kernels on `stream` (count, three scan passes, decode).  Errors:
+ * GNM_E_INVAL (null pointers, misaligned buffer or workspace, workspace too
+ * small, more than 2^31 datagrams), GNM_E_HIP.
+ */
+int gnm_netflow_v5_decode(const uint8_t *datagrams, uint64_t buf_bytes, const uint64_t *offsets,
+                          uint64_t n_datagrams, void *workspace, uint64_t workspace_bytes,
+                          const gnm_records_out *out, uint64_t *n_records, uint64_t *n_rejected,
+                          hipStream_t stream);
+
 /* Static description of an error code. */
 const char *gnm_strerror(int code);
 

@@ -38,6 +38,7 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
            "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_classify_aggregate",
            "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
+           "gnm_netflow_v5_workspace_bytes", "gnm_netflow_v5_decode",
            "gnm_strerror", "gnm_last_error", "gnm_version")
 TUNE_MAX = 16
 RATE_BUCKETS = 10001        # 10 kbps rate buckets per (site, direction) histogram
@@ -54,6 +55,13 @@ class RecordsC(ctypes.Structure):
                 ("src_port", ctypes.c_void_p), ("dst_port", ctypes.c_void_p), ("proto", ctypes.c_void_p),
                 ("bytes", ctypes.c_void_p), ("packets", ctypes.c_void_p),
                 ("first_ms", ctypes.c_void_p), ("last_ms", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class RecordsOutC(ctypes.Structure):
+    _fields_ = [("src_ip", ctypes.c_void_p), ("dst_ip", ctypes.c_void_p),
+                ("src_port", ctypes.c_void_p), ("dst_port", ctypes.c_void_p), ("proto", ctypes.c_void_p),
+                ("bytes", ctypes.c_void_p), ("packets", ctypes.c_void_p),
+                ("first_ms", ctypes.c_void_p), ("last_ms", ctypes.c_void_p), ("capacity", ctypes.c_uint64)]
 
 
 class Params(ctypes.Structure):
@@ -147,6 +155,11 @@ def lib():
         L.gnm_autotune.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32, ctypes.POINTER(Params), P,
                                    ctypes.c_uint32, P, ctypes.POINTER(TuneResult)]
         L.gnm_autotune.restype = ctypes.c_int
+        L.gnm_netflow_v5_workspace_bytes.argtypes = [ctypes.c_uint64]
+        L.gnm_netflow_v5_workspace_bytes.restype = ctypes.c_uint64
+        L.gnm_netflow_v5_decode.argtypes = [P, ctypes.c_uint64, P, ctypes.c_uint64, P, ctypes.c_uint64,
+                                            ctypes.POINTER(RecordsOutC), P, P, P]
+        L.gnm_netflow_v5_decode.restype = ctypes.c_int
         L.gnm_strerror.argtypes = [ctypes.c_int]
         L.gnm_strerror.restype = ctypes.c_char_p
         L.gnm_last_error.argtypes = []
@@ -434,6 +447,60 @@ def autotune(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1, r
              for i in range(out.n_tried)]
     return {"records_per_thread": int(out.best.records_per_thread), "grid_blocks": int(out.best.grid_blocks),
             "best_ms": float(out.best_ms), "tried": tried}
+
+
+OUT_FIELDS = {"src_ip": 4, "dst_ip": 4, "src_port": 2, "dst_port": 2, "proto": 1, "bytes": 8, "packets": 4,
+              "first_ms": 4, "last_ms": 4}
+
+
+def make_records_out(capacity: int, device=None, ports: bool = True) -> Dict[str, "object"]:
+    """Device tensors to decode up to `capacity` records into (ports and proto optional)."""
+    import torch
+    dt = {4: torch.int32, 2: torch.int16, 1: torch.uint8, 8: torch.int64}
+    dev = device if device is not None else "cuda"
+    return {f: torch.empty(int(capacity), dtype=dt[w], device=dev) for f, w in OUT_FIELDS.items()
+            if ports or f not in ("src_port", "dst_port", "proto")}
+
+
+def netflow_v5_workspace_bytes(n_datagrams: int) -> int:
+    return int(lib().gnm_netflow_v5_workspace_bytes(int(n_datagrams)))
+
+
+def netflow_v5_decode(datagrams, offsets, out: Dict[str, "object"], workspace=None, counts=None,
+                      stream=None):
+    """gnm_netflow_v5_decode: datagrams is a device uint8 tensor, offsets a
+    device 64-bit tensor of n+1 offsets, out a dict from make_records_out().
+    Returns a device int64 tensor [records carried, datagrams rejected]."""
+    import torch
+    n = offsets.numel() - 1
+    if n < 0 or offsets.element_size() != 8 or not offsets.is_cuda or not datagrams.is_cuda:
+        raise ValueError("offsets must be a device tensor of n+1 64-bit offsets; datagrams a device tensor")
+    cap = None
+    c = RecordsOutC()
+    for f, w in OUT_FIELDS.items():
+        t = out.get(f)
+        if t is None:
+            if f in ("src_port", "dst_port", "proto"):
+                continue
+            raise ValueError("missing output field %s" % f)
+        if not t.is_cuda or not t.is_contiguous() or t.element_size() != w:
+            raise ValueError("output field %s must be a contiguous device tensor of %d-byte items" % (f, w))
+        cap = t.numel() if cap is None else min(cap, t.numel())
+        setattr(c, f, t.data_ptr())
+    c.capacity = cap
+    need = netflow_v5_workspace_bytes(n)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=datagrams.device)
+    if counts is None:
+        counts = torch.empty(2, dtype=torch.int64, device=datagrams.device)
+    _check(lib().gnm_netflow_v5_decode(ctypes.c_void_p(datagrams.data_ptr()),
+                                       datagrams.numel() * datagrams.element_size(),
+                                       ctypes.c_void_p(offsets.data_ptr()), n,
+                                       ctypes.c_void_p(workspace.data_ptr()),
+                                       workspace.numel() * workspace.element_size(), ctypes.byref(c),
+                                       ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(counts.data_ptr() + 8),
+                                       _stream_handle(stream)), "gnm_netflow_v5_decode")
+    return counts
 
 
 def version() -> str:

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgnm.so")
-SOURCES = ["registry.cpp", "kernels.hip", "forms.cpp"]
+SOURCES = ["registry.cpp", "kernels.hip", "forms.cpp", "ingest.hip"]
 HEADERS = [os.path.join(INCLUDE, "gnm.h"), os.path.join(CSRC, "gnm_internal.h"),
            os.path.join(CSRC, "registry.h")]
 
