@@ -11,9 +11,10 @@
 //      sums of the counts (per-block totals, a one-block scan of those, then
 //      per-block rescans) give each datagram's first output record, and the
 //      totals of records and rejected datagrams;
-//   3. v5_decode_kernel: one wave per datagram, lane k decoding record k
-//      (eight of its twelve big-endian words) and writing each field with
-//      coalesced stores.
+//   3. v5_decode_kernel: one half-wave per datagram, lane k decoding record
+//      k (eight of its twelve big-endian words, with 8-byte loads when the
+//      record is 8-byte aligned, as back-to-back datagrams are) and writing
+//      each field with coalesced stores.
 // Field layout (public NetFlow version 5 export format, big-endian): header
 // of 24 bytes starting with version u16 and count u16; records of 48 bytes:
 // srcaddr, dstaddr, nexthop u32; input, output u16; dPkts, dOctets, First,
@@ -36,7 +37,8 @@ constexpr uint32_t kV5Record = 48;
 constexpr uint32_t kV5MaxRecords = 30;
 constexpr uint32_t kScanThreads = 1024;  // threads of the scan kernels
 constexpr uint32_t kScanBlocks = 1024;   // most blocks of the reduce and down-sweep passes
-constexpr uint32_t kDecodeWaves = 4;     // datagrams in flight per decode workgroup
+constexpr uint32_t kDecodeThreads = 256;                  // decode workgroup
+constexpr uint32_t kDecodeSlots = kDecodeThreads / 32u;   // one datagram per half-wave
 
 struct V5Out {
   uint32_t *src, *dst;
@@ -163,20 +165,35 @@ __global__ __launch_bounds__(kScanThreads) void v5_down_kernel(const uint32_t *_
   }
 }
 
-// One wave per datagram; lane k < count decodes record k of an accepted
-// datagram and writes it at base[d] + k (records past the capacity are
-// dropped; the reported total still counts them).
-__global__ __launch_bounds__(64 * kDecodeWaves) void v5_decode_kernel(const uint8_t *__restrict__ buf,
-                                                                      const uint64_t *__restrict__ off, uint64_t n,
-                                                                      const uint32_t *__restrict__ cnt,
-                                                                      const u64 *__restrict__ base, V5Out o) {
-  const uint32_t lane = threadIdx.x % 64u, wave = threadIdx.x / 64u;
-  for (uint64_t d = (uint64_t)blockIdx.x * kDecodeWaves + wave; d < n; d += (uint64_t)gridDim.x * kDecodeWaves) {
+// One half-wave per datagram; lane k < count of the half decodes record k
+// of an accepted datagram and writes it at base[d] + k (records past the
+// capacity are dropped; the reported total still counts them).
+__global__ __launch_bounds__(kDecodeThreads) void v5_decode_kernel(const uint8_t *__restrict__ buf,
+                                                                   const uint64_t *__restrict__ off, uint64_t n,
+                                                                   const uint32_t *__restrict__ cnt,
+                                                                   const u64 *__restrict__ base, V5Out o) {
+  const uint32_t k = threadIdx.x % 32u, slot = threadIdx.x / 32u;
+  for (uint64_t d = (uint64_t)blockIdx.x * kDecodeSlots + slot; d < n; d += (uint64_t)gridDim.x * kDecodeSlots) {
+    // the three per-datagram loads issue together (the offset and base of a
+    // rejected datagram are read but unused)
     const uint32_t c = cnt[d];
-    if (lane >= c) continue;
-    const uint32_t *r = (const uint32_t *)(buf + off[d] + kV5Header + (uint64_t)kV5Record * lane);
-    const uint32_t w0 = r[0], w1 = r[1], w4 = r[4], w5 = r[5], w6 = r[6], w7 = r[7], w8 = r[8], w9 = r[9];
-    const uint64_t i = base[d] + lane;
+    const uint64_t start = off[d], first = base[d];
+    if (k >= c) continue;
+    const uint8_t *rp = buf + start + kV5Header + (uint64_t)kV5Record * k;
+    uint32_t w0, w1, w4, w5, w6, w7, w8, w9;
+    if (((uintptr_t)rp & 7u) == 0u) {
+      const uint64_t *q = (const uint64_t *)rp;
+      const uint64_t a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 2),
+                     e = __builtin_nontemporal_load(q + 3), f = __builtin_nontemporal_load(q + 4);
+      w0 = (uint32_t)a; w1 = (uint32_t)(a >> 32);
+      w4 = (uint32_t)b; w5 = (uint32_t)(b >> 32);
+      w6 = (uint32_t)e; w7 = (uint32_t)(e >> 32);
+      w8 = (uint32_t)f; w9 = (uint32_t)(f >> 32);
+    } else {
+      const uint32_t *r = (const uint32_t *)rp;
+      w0 = r[0]; w1 = r[1]; w4 = r[4]; w5 = r[5]; w6 = r[6]; w7 = r[7]; w8 = r[8]; w9 = r[9];
+    }
+    const uint64_t i = first + k;
     if (i >= o.capacity) continue;
     o.src[i] = be32(w0);
     o.dst[i] = be32(w1);
@@ -256,8 +273,8 @@ extern "C" int gnm_netflow_v5_decode(const uint8_t *datagrams, uint64_t buf_byte
     int c = 0;
     if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0) cus = c;
   }
-  const uint64_t want = (n + kDecodeWaves - 1) / kDecodeWaves, cap = (uint64_t)cus * 32u;
-  hipLaunchKernelGGL(v5_decode_kernel, dim3((uint32_t)(want < cap ? want : cap)), dim3(64 * kDecodeWaves), 0,
+  const uint64_t want = (n + kDecodeSlots - 1) / kDecodeSlots, cap = (uint64_t)cus * 32u;
+  hipLaunchKernelGGL(v5_decode_kernel, dim3((uint32_t)(want < cap ? want : cap)), dim3(kDecodeThreads), 0,
                      stream, datagrams, offsets, n, (const uint32_t *)cnt, (const u64 *)base, o);
   if ((e = hipGetLastError()) != hipSuccess) return fail(e, "decode launch");
   return GNM_OK;
