@@ -23,6 +23,10 @@ the lower median; `median_flags` applies the two-window warning.  They are
 pinned against a per-record brute force and `statistics.median_low`, bucket
 closed forms and hand-worked flag sequences.
 
+Per-host statistics (`host_stats`): bulk-flow rate statistics per remote
+host and direction of the registered sites, pinned against a per-record brute
+force and against the site rows they add up to.
+
 NetFlow v5 decode (`oracle.netflow`): the step before the path, datagrams to
 SoA records, parsed with `struct`; pinned by a hand-built datagram, the
 paper's sizes, a round trip through the generator's numpy encoder and every
@@ -274,6 +278,38 @@ def rate_medians(reg: "Registry", rec, window_offsets=None, bulk_bytes: int = 1_
         med[w, rows_present] = b[start + (n + 1) // 2 - 1]
         cnt[w, rows_present] = n
     return med, cnt
+
+
+HOST_FIELDS = ("bulk_flows", "bulk_bytes", "rate_sum_bps", "rate_min_bps", "rate_max_bps")
+
+
+def host_stats(reg: "Registry", rec, bulk_bytes: int = 1_000_000, filters: Optional[dict] = None):
+    """Rate statistics per remote host of a registered site (§III.B.2: rates are
+    also computed for each host in a registered site), per direction.
+
+    Over the bulk flows of the registered (site, direction) rows: key =
+    remote address << 32 | row (row = 2 * site + direction; the remote
+    address is the source of an inbound flow, the destination of an outbound
+    one); per key the bulk flows, their bytes and rates (sum modulo 2^64,
+    min, max).  Returns (uint64 keys sorted ascending, uint64[n_keys, 5]).
+    """
+    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes, filters)
+    sel = is_bulk & (row < 2 * reg.n_sites)
+    remote = np.where(row % 2 == 0, np.asarray(rec.src_ip), np.asarray(rec.dst_ip))[sel]
+    key = (remote.astype(np.uint64) << np.uint64(32)) | row[sel].astype(np.uint64)
+    b = np.asarray(rec.bytes)[sel]
+    r = rate[sel]
+    order = np.argsort(key, kind="stable")
+    key, b, r = key[order], b[order], r[order]
+    keys, start = np.unique(key, return_index=True)
+    out = np.zeros((keys.size, 5), dtype=np.uint64)
+    if keys.size:
+        out[:, 0] = np.diff(np.append(start, key.size))
+        out[:, 1] = np.add.reduceat(b, start)         # uint64: wraps modulo 2^64
+        out[:, 2] = np.add.reduceat(r, start)
+        out[:, 3] = np.minimum.reduceat(r, start)
+        out[:, 4] = np.maximum.reduceat(r, start)
+    return keys, out
 
 
 def median_flags(med: np.ndarray, cnt: np.ndarray, n_sites: int, threshold_bps: int = 1_000_000,

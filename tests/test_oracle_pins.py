@@ -476,3 +476,64 @@ def test_filters_only_remove_rate_eligible_flows():
         assert (got[:, 6] >= prev[:, 6]).all() and (got[:, 7] <= prev[:, 7]).all()
         assert got[:, 4].sum() < prev[:, 4].sum()     # and removes some on this workload
         prev = got
+
+
+# ---------------------------------------------------------------- per-host statistics (§III.B.2)
+
+def _brute_hosts(sites, local, n_sites, recs, bulk_bytes, filters=None):
+    out = {}
+    for src, dst, b, p, f, l in recs:
+        dur = (l - f) & 0xFFFFFFFF
+        if not brute.is_bulk(b, p, dur, bulk_bytes, filters):
+            continue
+        row = brute.row_of(sites, local, n_sites, src, dst)
+        if row >= 2 * n_sites:
+            continue
+        remote = src if row % 2 == 0 else dst
+        rate = brute.rate_bps(b, dur)
+        e = out.setdefault((remote << 32) | row, [0, 0, 0, M64, 0])
+        e[0] += 1
+        e[1] = (e[1] + b) & M64
+        e[2] = (e[2] + rate) & M64
+        e[3] = min(e[3], rate)
+        e[4] = max(e[4], rate)
+    return out
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_host_stats_match_brute(seed):
+    rng = np.random.default_rng(2100 + seed)
+    n_sites, sites, local = random_tiny_registry(rng, n_local=int(rng.integers(1, 4)))
+    recs = _rate_records(rng, int(rng.integers(0, 300)), sites, local)
+    # repeat some remote hosts so hosts hold several flows
+    recs += [recs[int(i)] for i in rng.integers(0, len(recs), size=len(recs) // 2)] if recs else []
+    bulk = int(rng.choice([0, 1_000_000]))
+    filters = _random_filters(rng) if rng.random() < 0.3 else None
+    exp = _brute_hosts(sites, local, n_sites, recs, bulk, filters)
+    reg = _oracle_reg(sites, local, n_sites)
+    keys, st = oracle.host_stats(reg, soa(recs), bulk, filters)
+    assert sorted(exp) == keys.tolist()
+    assert [exp[k] for k in sorted(exp)] == st.tolist()
+
+
+def test_host_stats_add_up_to_the_site_rows():
+    reg = flowgen.registry_for(flowgen.PLAIN_LARGE)
+    rec = flowgen.records_for(flowgen.PLAIN_LARGE, reg=reg, n=300_000)
+    o = oracle.Registry.from_generated(reg)
+    rows = o.classify_aggregate(rec)
+    keys, st = oracle.host_stats(o, rec)
+    row_of_key = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    S2 = 2 * reg.n_sites
+    for field, col in ((4, 0), (5, 2)):   # bulk flows, rate sum
+        agg = np.zeros(S2, dtype=np.uint64)
+        np.add.at(agg, row_of_key, st[:, col])
+        assert (agg == rows[:S2, field]).all()
+    mn = np.full(S2, M64, dtype=np.uint64)
+    mx = np.zeros(S2, dtype=np.uint64)
+    np.minimum.at(mn, row_of_key, st[:, 3])
+    np.maximum.at(mx, row_of_key, st[:, 4])
+    assert (mn == rows[:S2, 6]).all() and (mx == rows[:S2, 7]).all()
+    # the remote address of a key lies in its site (the LPM answer for it is the key's site)
+    ips = (keys >> np.uint64(32)).astype(np.uint32)
+    assert (o.lookup(ips) == (row_of_key // 2).astype(np.uint32)).all()
+    assert keys.size > 10_000 and (st[:, 0] > 1).any()
