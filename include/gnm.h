@@ -123,6 +123,25 @@ typedef struct {
 #define GNM_RATE_BUCKET_BPS 10000u
 #define GNM_NO_MEDIAN 0xFFFFFFFFu /* median bucket of a row without bulk flows */
 
+/* Per-host statistics (§III.B.2, TransRate Kernel: transfer rates are also
+ * computed for each host in a registered site).  An open-addressing table in
+ * device memory, filled by the classify pass: one slot per (remote host,
+ * direction) of a registered site seen with at least one bulk flow, keyed
+ * by ((uint64_t)remote_address << 32) | (2*site + dir), where the remote
+ * address is the source of an inbound flow and the destination of an
+ * outbound one.  Per slot, stats[5*slot + f]: bulk flows, their bytes, rate
+ * sum (modulo 2^64), rate minimum, rate maximum.  Slot positions depend on
+ * timing; the set of (key, stats) does not, while the table has room.  With
+ * several windows in one call the table covers all of them. */
+#define GNM_HOST_EMPTY 0xFFFFFFFFFFFFFFFFull /* key of a free slot */
+typedef struct {
+  uint64_t *keys;     /* DEVICE [capacity], 8-byte aligned */
+  uint64_t *stats;    /* DEVICE [capacity * 5], 8-byte aligned */
+  uint64_t capacity;  /* a power of two, at most 2^40 */
+  uint64_t *counters; /* DEVICE [2]: [0] slots in use after the call; [1] bulk flows left out because
+                         every slot was taken by other hosts (their hosts are then absent) */
+} gnm_host_table;
+
 /* Per-call parameters.  Zero-initialise and set what you need;
  * gnm_params_default() gives bulk_bytes = 1,000,000 and automatic tuning. */
 typedef struct {
@@ -145,6 +164,9 @@ typedef struct {
   uint32_t min_packets;          /* bulk only with packets >= min_packets */
   uint32_t min_duration_ms;      /* bulk only with dur >= min_duration_ms (dur > 0 is always required) */
   uint32_t reserved2;
+  const gnm_host_table *hosts;   /* optional per-host statistics (host pointer to a table description):
+                                    NULL = none; else filled by the same pass (cleared first unless
+                                    GNM_ACCUMULATE) */
 } gnm_params;
 
 #define GNM_REG_HOST_ONLY 0x1u   /* gnm_registry_opts.flags: build host structure only */
@@ -269,11 +291,15 @@ uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks);
  * classify kernel, and (with a usable p->workspace) the reduce kernel.  With
  * p->rate_hist, each bulk flow of a registered site also adds one to its
  * row's histogram with a device-scope 32-bit atomic; the caller owns the
- * histogram memory (n_windows * 2 * n_sites * GNM_RATE_BUCKETS * 4 bytes).  Each classify workgroup walks a balanced contiguous slice of all
+ * histogram memory (n_windows * 2 * n_sites * GNM_RATE_BUCKETS * 4 bytes).
+ * With p->hosts, each such flow also updates its host's slot (a device-scope
+ * compare-and-swap to claim it, then five device-scope atomics), the table
+ * is cleared first (unless accumulating) and its slots in use are counted
+ * after the classify kernel.  Each classify workgroup walks a balanced contiguous slice of all
  * records, flushing its LDS table at window changes.  Errors: GNM_E_INVAL
  * (null pointers, n_windows = 0, offsets NULL with n_windows > 1,
  * records_per_thread not 0/1/2/4, n_windows tables beyond 2^39 words,
- * rate_hist not 16-byte aligned), GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
+ * rate_hist not 16-byte aligned, a malformed host table), GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
  */
 int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
                            const uint64_t *window_offsets, uint32_t n_windows,

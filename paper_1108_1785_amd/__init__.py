@@ -70,7 +70,42 @@ class Params(ctypes.Structure):
                 ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_uint64), ("rate_hist", ctypes.c_void_p),
                 ("min_avg_packet_bytes", ctypes.c_uint32), ("min_packets", ctypes.c_uint32),
-                ("min_duration_ms", ctypes.c_uint32), ("reserved2", ctypes.c_uint32)]
+                ("min_duration_ms", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
+                ("hosts", ctypes.c_void_p)]
+
+
+class HostTableC(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("counters", ctypes.c_void_p)]
+
+
+HOST_EMPTY = 0xFFFFFFFFFFFFFFFF
+HOST_FIELDS = ("bulk_flows", "bulk_bytes", "rate_sum_bps", "rate_min_bps", "rate_max_bps")
+
+
+class HostTable:
+    """Device per-host statistics table (gnm_host_table) of `capacity` slots (a power of two)."""
+
+    def __init__(self, capacity: int, device=None):
+        import torch
+        capacity = int(capacity)
+        if capacity <= 0 or capacity & (capacity - 1):
+            raise ValueError("capacity must be a power of two")
+        dev = device if device is not None else "cuda"
+        self.capacity = capacity
+        self.keys = torch.empty(capacity, dtype=torch.int64, device=dev)
+        self.stats = torch.empty((capacity, 5), dtype=torch.int64, device=dev)
+        self.counters = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.c = HostTableC(self.keys.data_ptr(), self.stats.data_ptr(), capacity, self.counters.data_ptr())
+
+    def to_numpy(self):
+        """(keys sorted ascending, stats [n, 5], hosts counted, flows left out), uint64."""
+        k = self.keys.cpu().numpy().view(np.uint64)
+        st = self.stats.cpu().numpy().view(np.uint64)
+        used = k != np.uint64(HOST_EMPTY)
+        order = np.argsort(k[used], kind="stable")
+        cnt = self.counters.cpu().numpy().view(np.uint64)
+        return k[used][order], st[used][order], int(cnt[0]), int(cnt[1])
 
 
 FILTER_KEYS = ("min_avg_packet_bytes", "min_packets", "min_duration_ms")
@@ -278,8 +313,9 @@ def records_struct(rec: Dict[str, "object"], n: Optional[int] = None) -> Records
 
 
 def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_per_thread: int = 0,
-                grid_blocks: int = 0, workspace=None, rate_hist=None, filters=None) -> Params:
-    """filters: optional dict of exclusion thresholds (FILTER_KEYS), 0 = off."""
+                grid_blocks: int = 0, workspace=None, rate_hist=None, filters=None, hosts=None) -> Params:
+    """filters: optional dict of exclusion thresholds (FILTER_KEYS), 0 = off.
+    hosts: optional HostTable (the caller keeps it alive while work is queued)."""
     p = lib().gnm_params_default()
     p.bulk_bytes = int(bulk_bytes)
     p.flags = GNM_ACCUMULATE if accumulate else 0
@@ -302,6 +338,10 @@ def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_p
         if not 0 <= v < 2**32:
             raise ValueError("%s must fit 32 bits" % k)
         setattr(p, k, v)
+    if hosts is not None:
+        if not isinstance(hosts, HostTable):
+            raise ValueError("hosts must be a HostTable")
+        p.hosts = ctypes.addressof(hosts.c)
     return p
 
 
@@ -332,12 +372,14 @@ def make_workspace(reg: Registry, grid_blocks: int = 0, device=None):
 def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1,
                        bulk_bytes: int = 1_000_000, accumulate: bool = False,
                        records_per_thread: int = 0, grid_blocks: int = 0, stream=None,
-                       n: Optional[int] = None, workspace=None, rate_hist=None, filters=None) -> None:
+                       n: Optional[int] = None, workspace=None, rate_hist=None, filters=None,
+                       hosts=None) -> None:
     """gnm_classify_aggregate: acc is a device tensor of n_windows*rows*8 64-bit words.
 
     workspace: optional device tensor from make_workspace() (faster table merge).
     rate_hist: optional device tensor from make_rate_hist() (bulk-rate histograms).
     filters: optional exclusion thresholds, e.g. {"min_avg_packet_bytes": 100}.
+    hosts: optional HostTable for per-host statistics.
     """
     c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
     if acc.element_size() * acc.numel() < n_windows * reg.rows * 64 or not acc.is_cuda:
@@ -349,7 +391,7 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
         off = window_offsets.data_ptr()
     if rate_hist is not None and rate_hist.numel() < rate_hist_words(reg, n_windows):
         raise ValueError("rate_hist must hold n_windows * 2 * n_sites * 10001 counts")
-    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist, filters)
+    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist, filters, hosts)
     _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
                                         ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
                                         _stream_handle(stream)), "gnm_classify_aggregate")
@@ -403,7 +445,8 @@ class Graph:
 
     def __init__(self, reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1, flags=None,
                  threshold_bps: int = 1_000_000, min_bulk_flows: int = 0, n: Optional[int] = None, **params):
-        self._keep = (reg, rec, acc, window_offsets, flags, params.get("workspace"), params.get("rate_hist"))
+        self._keep = (reg, rec, acc, window_offsets, flags, params.get("workspace"), params.get("rate_hist"),
+                      params.get("hosts"))
         self._rec = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
         self._p = make_params(**params)
         off = 0 if window_offsets is None else window_offsets.data_ptr()

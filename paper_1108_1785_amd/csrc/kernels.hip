@@ -57,6 +57,10 @@ constexpr uint32_t kRedGroups = 16;  // reduce kernel: waves, each summing every
 constexpr uint32_t kRedUnroll = 8;   // reduce kernel: slot loads in flight per lane
 constexpr uint32_t kBuckets = 10001;      // rate histogram: 10 kbps buckets, the last for > 100 Mbps
 constexpr uint32_t kBucketBps = 10000;
+constexpr uint32_t kFeatHist = 1;         // classify_kernel FEAT bits: rate histograms,
+constexpr uint32_t kFeatHosts = 2;        //   per-host statistics
+constexpr uint64_t kHostEmpty = ~0ull;    // free slot of the host table
+constexpr uint32_t kHostFields = 5;       // bulk flows, bulk bytes, rate sum, min, max
 constexpr uint32_t kHistKeyBits = 14;     // LDS histogram cache key: row << 14 | bucket
 constexpr uint32_t kHistSlotsMax = 4096;  // LDS histogram cache slots (8 bytes each, 4-way sets)
 constexpr uint32_t kMedWaves = 4;         // median kernel: one wave per (window, site), 4 per workgroup
@@ -91,9 +95,13 @@ struct ClassifyArgs {
   uint32_t cache_slots;  // LDS cache slots for a table that does not fit in LDS
   u64 *ws;             // NULL: every table is flushed with atomics
   uint32_t *ws_meta;   // per workgroup: window of the table it left in ws
-  uint32_t *hist;      // rate histograms: n_windows * hist_rows * kBuckets counts (HIST variants)
+  uint32_t *hist;      // rate histograms: n_windows * hist_rows * kBuckets counts (FEAT & kFeatHist)
   uint32_t hist_rows;  // 2 * n_sites: rows of registered sites
   uint32_t lds_off_hist, hist_slots;  // LDS histogram cache (0 slots: every count goes to device memory)
+  uint64_t *host_keys;                // host table (FEAT & kFeatHosts): keys, then 5 words per slot
+  u64 *host_stats;
+  uint64_t host_mask;                 // capacity - 1 (a power of two)
+  u64 *host_counters;                 // [0] hosts (written by the count kernel), [1] flows left out
   uint32_t filters;                   // any exclusion filter set
   uint32_t min_avg_packet_bytes, min_packets, min_duration_ms;
   LocalRanges local;
@@ -632,16 +640,50 @@ __device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyAr
 }
 
 // Aggregate the tile's classified records.
+// Finalizer of splitmix64: spreads the host keys over the table.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// Add one bulk flow to the host table (open addressing, linear probing).  A
+// slot's key is claimed with a device-scope compare-and-swap and never
+// changes afterwards, so a non-empty key read with a plain load is current;
+// an empty one may be stale, which the compare-and-swap settles.  When every
+// slot is taken by other hosts the flow is counted as left out.
+__device__ __forceinline__ void host_add(const ClassifyArgs &a, uint64_t key, uint64_t bytes, uint64_t rate) {
+  uint64_t h = mix64(key) & a.host_mask;
+  for (uint64_t probe = 0; probe <= a.host_mask; ++probe) {
+    uint64_t cur = a.host_keys[h];
+    if (cur == kHostEmpty) cur = atomicCAS((u64 *)&a.host_keys[h], (u64)kHostEmpty, (u64)key);
+    if (cur == kHostEmpty || cur == key) {
+      u64 *st = a.host_stats + h * kHostFields;
+      __hip_atomic_fetch_add(&st[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&st[1], (u64)bytes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&st[2], (u64)rate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      atomicMin(&st[3], (u64)rate);
+      atomicMax(&st[4], (u64)rate);
+      return;
+    }
+    h = (h + 1u) & a.host_mask;
+  }
+  __hip_atomic_fetch_add(&a.host_counters[1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Histogram bucket of a rate: floor(rate / 10 kbps), at most the last bucket.
 __device__ __forceinline__ uint32_t rate_bucket(uint64_t rate) {
   constexpr uint64_t kTop = (uint64_t)kBucketBps * (kBuckets - 1u);  // 100 Mbps
   return rate >= kTop ? kBuckets - 1u : (uint32_t)rate / kBucketBps;
 }
 
-template <int R, bool ACC_LDS, bool HIST>
-__device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uint32_t (&row)[R], const Rest<R> &r,
+template <int R, bool ACC_LDS, uint32_t FEAT>
+__device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t (&row)[R], const Rest<R> &r,
                                                const ClassifyArgs &a, const Lds &L, u64 *g_tab,
                                                uint32_t *h_tab) {
+  const bool(&valid)[R] = t.v;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const uint32_t dur = r.l[k] - r.f[k];
@@ -661,17 +703,21 @@ __device__ __forceinline__ void aggregate_tile(const bool (&valid)[R], const uin
       add_rate<ACC_LDS>(L, g_tab, code, rate);
       // count in the row's histogram: registered sites only (not the
       // "no site" rows or NODIR)
-      if (HIST && row[k] < a.hist_rows) hist_add(L, h_tab, row[k], rate_bucket(rate));
+      if ((FEAT & kFeatHist) && row[k] < a.hist_rows) hist_add(L, h_tab, row[k], rate_bucket(rate));
+      // per-host statistics: the remote endpoint (the source of an inbound
+      // flow, the destination of an outbound one) of a registered site
+      if ((FEAT & kFeatHosts) && row[k] < a.hist_rows)
+        host_add(a, ((uint64_t)((row[k] & 1u) ? t.d[k] : t.s[k]) << 32) | row[k], r.b[k], rate);
     }
   }
 }
 
-template <int R, bool LINES_LDS, bool ACC_LDS, bool HIST>
+template <int R, bool LINES_LDS, bool ACC_LDS, uint32_t FEAT>
 __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r, const ClassifyArgs &a,
                                              const Lds &L, u64 *g_tab, uint32_t *h_tab) {
   uint32_t row[R];
   classify_tile<R, LINES_LDS>(t, a, L, row);
-  aggregate_tile<R, ACC_LDS, HIST>(t.v, row, r, a, L, g_tab, h_tab);
+  aggregate_tile<R, ACC_LDS, FEAT>(t, row, r, a, L, g_tab, h_tab);
 }
 
 // Records [lo, hi) of one window: tiles whose addresses are prefetched one
@@ -679,7 +725,7 @@ __device__ __forceinline__ void process_tile(const Addr<R> &t, const Rest<R> &r,
 // overlaps the locality tests and the trie walk.  (Measured: prefetching the
 // other fields a tile ahead as well, or in the middle of the walk, gained
 // nothing at 4 waves per SIMD.)
-template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS, bool HIST>
+template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS, uint32_t FEAT>
 __device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &L, u64 *g_tab, uint32_t *h_tab,
                                               uint64_t lo, uint64_t hi) {
   constexpr uint64_t T = (uint64_t)kThreads * R;
@@ -692,7 +738,7 @@ __device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &
     load_addr<R, VEC>(nxt, a, base + T, hi);  // past the end: reloads the last records, marked invalid
     uint32_t row[R];
     classify_tile<R, LINES_LDS>(cur, a, L, row);
-    aggregate_tile<R, ACC_LDS, HIST>(cur.v, row, rest, a, L, g_tab, h_tab);
+    aggregate_tile<R, ACC_LDS, FEAT>(cur, row, rest, a, L, g_tab, h_tab);
     cur = nxt;
   }
 }
@@ -702,6 +748,36 @@ __device__ __forceinline__ void process_range(const ClassifyArgs &a, const Lds &
 __global__ void init_acc_kernel(u64 *__restrict__ acc, uint64_t words) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < words) acc[i] = ((i & 7u) == 6u) ? ~0ull : 0ull;
+}
+
+// Host table: free every slot (key empty, statistics zero, minimum at the
+// maximum), grid-stride.
+__global__ void host_init_kernel(uint64_t *__restrict__ keys, u64 *__restrict__ stats, uint64_t cap) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+    keys[i] = kHostEmpty;
+    u64 *st = stats + i * kHostFields;
+    st[0] = 0;
+    st[1] = 0;
+    st[2] = 0;
+    st[3] = ~0ull;
+    st[4] = 0;
+  }
+}
+
+// counters[0] = 0, and counters[1] = 0 too unless accumulating.
+__global__ void host_reset_kernel(u64 *counters, uint32_t accumulate) {
+  counters[0] = 0;
+  if (!accumulate) counters[1] = 0;
+}
+
+// counters[0] += slots in use: one device atomic per wave.
+__global__ void host_count_kernel(const uint64_t *__restrict__ keys, uint64_t cap, u64 *counters) {
+  u64 c = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x)
+    c += keys[i] != kHostEmpty;
+#pragma unroll
+  for (uint32_t o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (threadIdx.x % 64u == 0u && c) __hip_atomic_fetch_add(&counters[0], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Zero n 32-bit words at a 16-byte aligned address: four per lane, grid-stride.
@@ -717,8 +793,9 @@ __global__ void zero_words_kernel(uint32_t *__restrict__ p, uint64_t n) {
   }
 }
 
-template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS, bool HIST>
+template <int R, bool VEC, bool LINES_LDS, bool ACC_LDS, uint32_t FEAT>
 __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a) {
+  constexpr bool HIST = (FEAT & kFeatHist) != 0;
   extern __shared__ __align__(16) unsigned char lds[];
   uint64_t *s_root = (uint64_t *)lds;
   u64 *s_acc = (u64 *)(lds + a.lds_off_acc);
@@ -773,11 +850,11 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
         Rest<R> mr;
         const bool head = tid < a0 - i, tail = tid >= 3 && tid - 3 < seg_end - a1;
         load_single(m, mr, a, head ? i + tid : a1 + (tid - 3), head || tail);
-        process_tile<R, LINES_LDS, ACC_LDS, HIST>(m, mr, a, L, g_tab, h_tab);
+        process_tile<R, LINES_LDS, ACC_LDS, FEAT>(m, mr, a, L, g_tab, h_tab);
       }
-      if (a0 < a1) process_range<4, true, LINES_LDS, ACC_LDS, HIST>(a, L, g_tab, h_tab, a0, a1);
+      if (a0 < a1) process_range<4, true, LINES_LDS, ACC_LDS, FEAT>(a, L, g_tab, h_tab, a0, a1);
     } else {
-      process_range<R, false, LINES_LDS, ACC_LDS, HIST>(a, L, g_tab, h_tab, i, seg_end);
+      process_range<R, false, LINES_LDS, ACC_LDS, FEAT>(a, L, g_tab, h_tab, i, seg_end);
     }
     if (ACC_LDS) {
       if (seg_end >= hi && a.ws) flush_partial(a, s_acc, w);
@@ -1057,31 +1134,36 @@ int device_cus(int dev) {
 
 typedef void (*KernelFn)(const ClassifyArgs);
 
-// variant slot: hist * 16 + shape * 4 + lists * 2 + acc; shapes: R=1, R=2, R=4 strided, R=4 vector
-template <int R, bool V, bool H>
+// variant slot: feat * 16 + shape * 4 + lists * 2 + acc; shapes: R=1, R=2, R=4 strided, R=4 vector
+template <int R, bool V, uint32_t F>
 KernelFn pick_la(bool lists, bool acc) {
-  if (lists) return acc ? classify_kernel<R, V, true, true, H> : classify_kernel<R, V, true, false, H>;
-  return acc ? classify_kernel<R, V, false, true, H> : classify_kernel<R, V, false, false, H>;
+  if (lists) return acc ? classify_kernel<R, V, true, true, F> : classify_kernel<R, V, true, false, F>;
+  return acc ? classify_kernel<R, V, false, true, F> : classify_kernel<R, V, false, false, F>;
 }
 
-template <bool H>
+template <uint32_t F>
 KernelFn pick_shape(int shape, bool lists, bool acc) {
   switch (shape) {
-    case 0: return pick_la<1, false, H>(lists, acc);
-    case 1: return pick_la<2, false, H>(lists, acc);
-    case 2: return pick_la<4, false, H>(lists, acc);
-    default: return pick_la<4, true, H>(lists, acc);
+    case 0: return pick_la<1, false, F>(lists, acc);
+    case 1: return pick_la<2, false, F>(lists, acc);
+    case 2: return pick_la<4, false, F>(lists, acc);
+    default: return pick_la<4, true, F>(lists, acc);
   }
 }
 
-KernelFn pick(int shape, bool lists, bool acc, bool hist) {
-  return hist ? pick_shape<true>(shape, lists, acc) : pick_shape<false>(shape, lists, acc);
+KernelFn pick(int shape, bool lists, bool acc, uint32_t feat) {
+  switch (feat) {
+    case 0: return pick_shape<0>(shape, lists, acc);
+    case kFeatHist: return pick_shape<kFeatHist>(shape, lists, acc);
+    case kFeatHosts: return pick_shape<kFeatHosts>(shape, lists, acc);
+    default: return pick_shape<kFeatHist | kFeatHosts>(shape, lists, acc);
+  }
 }
 
 // Allow every kernel variant the full 160 KB of LDS, once per device.
 hipError_t allow_lds(KernelFn fn, int slot, int dev) {
   static std::mutex mu;
-  static bool done[64][32] = {};
+  static bool done[64][64] = {};
   std::lock_guard<std::mutex> g(mu);
   if (dev >= 0 && dev < 64 && done[dev][slot]) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
@@ -1150,6 +1232,13 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     set_last_error("rate_hist must be 16-byte aligned");
     return GNM_E_INVAL;
   }
+  const gnm_host_table *ht = p.hosts;
+  if (ht && (!ht->keys || !ht->stats || !ht->counters || ht->capacity == 0 ||
+             (ht->capacity & (ht->capacity - 1)) != 0 || ht->capacity > (1ull << 40) ||
+             ((uintptr_t)ht->keys & 7u) || ((uintptr_t)ht->stats & 7u) || ((uintptr_t)ht->counters & 7u))) {
+    set_last_error("host table: NULL or misaligned arrays, or a capacity that is not a power of two up to 2^40");
+    return GNM_E_INVAL;
+  }
   const uint64_t word_tiles = (kAccFields * rows + kRedWords - 1) / kRedWords;
   const bool use_ws = rec->n > 0 && reg->acc_in_lds && p.workspace &&
                       p.workspace_bytes >= partial_bytes(reg, grid) && aligned16(p.workspace) &&
@@ -1167,6 +1256,17 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "init launch");
   }
+  if (ht) {
+    hipLaunchKernelGGL(host_reset_kernel, dim3(1), dim3(1), 0, stream, (u64 *)ht->counters,
+                       (p.flags & GNM_ACCUMULATE) ? 1u : 0u);
+    if (!(p.flags & GNM_ACCUMULATE)) {
+      const uint64_t cap = (uint64_t)device_cus(dev) * 64u, blocks = (ht->capacity + 255u) / 256u;
+      hipLaunchKernelGGL(host_init_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(256), 0, stream,
+                         ht->keys, (u64 *)ht->stats, ht->capacity);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "host table init launch");
+  }
   if (p.rate_hist && !(p.flags & GNM_ACCUMULATE)) {
     const uint64_t quads = (hist_words + 3u) / 4u;
     const uint64_t cap = (uint64_t)device_cus(dev) * 64u;
@@ -1176,7 +1276,16 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "histogram init launch");
   }
-  if (rec->n == 0) return GNM_OK;
+  // slots in use, counted after the classify launch (and on an empty run)
+  auto count_hosts = [&]() -> int {
+    if (!ht) return GNM_OK;
+    const uint64_t cap = (uint64_t)device_cus(dev) * 16u, blocks = (ht->capacity + 255u) / 256u;
+    hipLaunchKernelGGL(host_count_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(256), 0, stream,
+                       (const uint64_t *)ht->keys, ht->capacity, (u64 *)ht->counters);
+    const hipError_t e2 = hipGetLastError();
+    return e2 == hipSuccess ? GNM_OK : hip_fail(e2, "host count launch");
+  };
+  if (rec->n == 0) return count_hosts();
 
   ClassifyArgs a{};
   a.src = rec->src_ip; a.dst = rec->dst_ip; a.bytes = rec->bytes; a.packets = rec->packets;
@@ -1192,6 +1301,12 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.cache_slots = reg->acc_in_lds ? 0u : reg->cache_slots;
   a.hist = p.rate_hist;
   a.hist_rows = 2u * reg->n_sites;
+  if (ht) {
+    a.host_keys = ht->keys;
+    a.host_stats = (u64 *)ht->stats;
+    a.host_mask = ht->capacity - 1u;
+    a.host_counters = (u64 *)ht->counters;
+  }
   uint32_t lds_launch = reg->lds_bytes;
   if (p.rate_hist) {
     // the histogram cache takes the LDS the registry leaves free, within the
@@ -1218,9 +1333,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   const bool vec = R == 4 && aligned16(rec->src_ip) && aligned16(rec->dst_ip) && aligned16(rec->bytes) &&
                    aligned16(rec->packets) && aligned16(rec->first_ms) && aligned16(rec->last_ms);
   const int shape = vec ? 3 : (R == 1 ? 0 : (R == 2 ? 1 : 2));
-  KernelFn fn = pick(shape, reg->lines_in_lds, reg->acc_in_lds, p.rate_hist != nullptr);
-  e = allow_lds(fn, (p.rate_hist ? 16 : 0) + shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0),
-                dev);
+  const uint32_t feat = (p.rate_hist ? kFeatHist : 0u) | (p.hosts ? kFeatHosts : 0u);
+  KernelFn fn = pick(shape, reg->lines_in_lds, reg->acc_in_lds, feat);
+  e = allow_lds(fn, (int)feat * 16 + shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0), dev);
   if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), lds_launch, stream, a);
   e = hipGetLastError();
@@ -1232,7 +1347,7 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
   }
-  return GNM_OK;
+  return count_hosts();
 }
 
 extern "C" int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_windows,
