@@ -28,6 +28,8 @@ Beside the headline line, the other forms:
   (30 records per datagram, some partial), resident in HBM, decoded into the
   record arrays; then the same decode followed by classify/aggregate and the
   flag kernel on the decoded window;
+* hosts: the plain step with per-host statistics (an open-addressing table
+  of 2^21 slots for the remote hosts of the registered sites);
 * served: open-loop Poisson arrivals (200 windows/s, lognormal sizes with
   median 300 k records, capped at 5 M) through the request loop, host records
   copied in over PCIe; p50/p99 latency from scheduled arrival to result;
@@ -451,6 +453,29 @@ def main():
                                             float(np.mean(icms))))
     del d_v5, v5_ws
 
+    # ---------------------------------------------------------------- per-host statistics
+    host_t = gnm.HostTable(1 << 21, device=dev)
+    kw_h = dict(kw, hosts=host_t)
+    hstep = [0]
+
+    def hosts_call():
+        gnm.classify_aggregate(reg, structs[hstep[0] % args.windows], acc, **kw_h)
+        hstep[0] += 1
+
+    for _ in range(args.warmup):
+        hosts_call()
+    wall_h, hms = timed_events(hosts_call, args.steps, torch)
+    hk = float(np.mean(hms))
+    gnm.classify_aggregate(reg, structs[0], acc, **kw_h)
+    torch.cuda.synchronize()
+    got_hosts = host_t.to_numpy()
+    forms["hosts"] = {"records_per_s": args.steps * n_win / wall_h, "call_ms_avg": hk, "plain_call_ms_avg": k_avg,
+                      "table_slots": host_t.capacity, "hosts_window0": got_hosts[2],
+                      "launch": "classify call with a per-host table: clear, classify, merge, count"}
+    log("hosts: classify call with per-host statistics %.4f ms (plain %.4f), %d hosts in window 0" %
+        (hk, k_avg, got_hosts[2]))
+    del host_t
+
     # ---------------------------------------------------------------- exclusion filters
     filt = {"min_avg_packet_bytes": 100, "min_packets": 1000, "min_duration_ms": 5000}
     kw_f = dict(kw, filters=filt)
@@ -665,6 +690,11 @@ def main():
         if not (got_v5_acc == orc.classify_aggregate(v5_rec)).all():
             bad.append("ingest + classify")
         parity_notes["ingest"] = "all 10M decoded records vs their source; 200 datagrams vs the oracle decoder; table"
+        hk_, hs_ = oracle.host_stats(orc, parts[0])
+        if got_hosts[3] != 0 or got_hosts[2] != hk_.size or not (got_hosts[0] == hk_).all() or \
+                not (got_hosts[1] == hs_).all():
+            bad.append("hosts")
+        parity_notes["hosts"] = "every host of window 0"
         exp_f = orc.classify_aggregate(parts[0], filters=filt)
         if not (got_f == exp_f).all():
             bad.append("filtered")

@@ -131,13 +131,13 @@ typedef struct {
  * address is the source of an inbound flow and the destination of an
  * outbound one.  Per slot, stats[5*slot + f]: bulk flows, their bytes, rate
  * sum (modulo 2^64), rate minimum, rate maximum.  Slot positions depend on
- * timing; the set of (key, stats) does not, while the table has room.  With
- * several windows in one call the table covers all of them. */
+ * timing; the set of (key, statistics) does not, while the table has room.
+ * With several windows in one call the table covers all of them. */
 #define GNM_HOST_EMPTY 0xFFFFFFFFFFFFFFFFull /* key of a free slot */
 typedef struct {
   uint64_t *keys;     /* DEVICE [capacity], 8-byte aligned */
   uint64_t *stats;    /* DEVICE [capacity * 5], 8-byte aligned */
-  uint64_t capacity;  /* a power of two, at most 2^40 */
+  uint64_t capacity;  /* a power of two, at most 2^36 */
   uint64_t *counters; /* DEVICE [2]: [0] slots in use after the call; [1] bulk flows left out because
                          every slot was taken by other hosts (their hosts are then absent) */
 } gnm_host_table;

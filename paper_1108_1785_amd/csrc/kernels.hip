@@ -60,7 +60,7 @@ constexpr uint32_t kBucketBps = 10000;
 constexpr uint32_t kFeatHist = 1;         // classify_kernel FEAT bits: rate histograms,
 constexpr uint32_t kFeatHosts = 2;        //   per-host statistics
 constexpr uint64_t kHostEmpty = ~0ull;    // free slot of the host table
-constexpr uint32_t kHostFields = 5;       // bulk flows, bulk bytes, rate sum, min, max
+constexpr uint32_t kHostFields = 5;       // host statistics: bulk flows, bytes, rate sum, min, max
 constexpr uint32_t kHistKeyBits = 14;     // LDS histogram cache key: row << 14 | bucket
 constexpr uint32_t kHistSlotsMax = 4096;  // LDS histogram cache slots (8 bytes each, 4-way sets)
 constexpr uint32_t kMedWaves = 4;         // median kernel: one wave per (window, site), 4 per workgroup
@@ -98,8 +98,8 @@ struct ClassifyArgs {
   uint32_t *hist;      // rate histograms: n_windows * hist_rows * kBuckets counts (FEAT & kFeatHist)
   uint32_t hist_rows;  // 2 * n_sites: rows of registered sites
   uint32_t lds_off_hist, hist_slots;  // LDS histogram cache (0 slots: every count goes to device memory)
-  uint64_t *host_keys;                // host table (FEAT & kFeatHosts): keys, then 5 words per slot
-  u64 *host_stats;
+  u64 *host_keys;                     // host table (FEAT & kFeatHosts): keys,
+  u64 *host_stats;                    //   and 5 statistics words per slot
   uint64_t host_mask;                 // capacity - 1 (a power of two)
   u64 *host_counters;                 // [0] hosts (written by the count kernel), [1] flows left out
   uint32_t filters;                   // any exclusion filter set
@@ -649,16 +649,19 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// Add one bulk flow to the host table (open addressing, linear probing).  A
-// slot's key is claimed with a device-scope compare-and-swap and never
-// changes afterwards, so a non-empty key read with a plain load is current;
-// an empty one may be stale, which the compare-and-swap settles.  When every
-// slot is taken by other hosts the flow is counted as left out.
+// Add one bulk flow to the host table (open addressing, linear probing over
+// the key array).  A slot's key is claimed with a device-scope
+// compare-and-swap and never changes afterwards, so a non-empty key read with
+// a plain load is current; an empty one may be stale, which the
+// compare-and-swap settles.  When every slot is taken by other hosts the flow
+// is counted as left out.  (Keys and statistics in one 64-byte slot measured
+// the same here and cost more to clear and count: the six device-scope
+// operations per flow set the pace.)
 __device__ __forceinline__ void host_add(const ClassifyArgs &a, uint64_t key, uint64_t bytes, uint64_t rate) {
   uint64_t h = mix64(key) & a.host_mask;
   for (uint64_t probe = 0; probe <= a.host_mask; ++probe) {
     uint64_t cur = a.host_keys[h];
-    if (cur == kHostEmpty) cur = atomicCAS((u64 *)&a.host_keys[h], (u64)kHostEmpty, (u64)key);
+    if (cur == kHostEmpty) cur = atomicCAS(&a.host_keys[h], (u64)kHostEmpty, (u64)key);
     if (cur == kHostEmpty || cur == key) {
       u64 *st = a.host_stats + h * kHostFields;
       __hip_atomic_fetch_add(&st[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -752,7 +755,7 @@ __global__ void init_acc_kernel(u64 *__restrict__ acc, uint64_t words) {
 
 // Host table: free every slot (key empty, statistics zero, minimum at the
 // maximum), grid-stride.
-__global__ void host_init_kernel(uint64_t *__restrict__ keys, u64 *__restrict__ stats, uint64_t cap) {
+__global__ void host_init_kernel(u64 *__restrict__ keys, u64 *__restrict__ stats, uint64_t cap) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
     keys[i] = kHostEmpty;
     u64 *st = stats + i * kHostFields;
@@ -770,14 +773,21 @@ __global__ void host_reset_kernel(u64 *counters, uint32_t accumulate) {
   if (!accumulate) counters[1] = 0;
 }
 
-// counters[0] += slots in use: one device atomic per wave.
-__global__ void host_count_kernel(const uint64_t *__restrict__ keys, uint64_t cap, u64 *counters) {
+// counters[0] += slots in use: a few hundred workgroups, each summing in LDS
+// and adding once (device-scope atomics on one address serialise).
+__global__ __launch_bounds__(256) void host_count_kernel(const u64 *__restrict__ keys, uint64_t cap, u64 *counters) {
+  __shared__ u64 part[4];
   u64 c = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x)
     c += keys[i] != kHostEmpty;
 #pragma unroll
   for (uint32_t o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if (threadIdx.x % 64u == 0u && c) __hip_atomic_fetch_add(&counters[0], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x % 64u == 0u) part[threadIdx.x / 64u] = c;
+  __syncthreads();
+  if (threadIdx.x == 0u) {
+    const u64 t = part[0] + part[1] + part[2] + part[3];
+    if (t) __hip_atomic_fetch_add(&counters[0], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Zero n 32-bit words at a 16-byte aligned address: four per lane, grid-stride.
@@ -1234,9 +1244,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   }
   const gnm_host_table *ht = p.hosts;
   if (ht && (!ht->keys || !ht->stats || !ht->counters || ht->capacity == 0 ||
-             (ht->capacity & (ht->capacity - 1)) != 0 || ht->capacity > (1ull << 40) ||
+             (ht->capacity & (ht->capacity - 1)) != 0 || ht->capacity > (1ull << 36) ||
              ((uintptr_t)ht->keys & 7u) || ((uintptr_t)ht->stats & 7u) || ((uintptr_t)ht->counters & 7u))) {
-    set_last_error("host table: NULL or misaligned arrays, or a capacity that is not a power of two up to 2^40");
+    set_last_error("host table: NULL or misaligned arrays, or a capacity that is not a power of two up to 2^36");
     return GNM_E_INVAL;
   }
   const uint64_t word_tiles = (kAccFields * rows + kRedWords - 1) / kRedWords;
@@ -1262,7 +1272,7 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     if (!(p.flags & GNM_ACCUMULATE)) {
       const uint64_t cap = (uint64_t)device_cus(dev) * 64u, blocks = (ht->capacity + 255u) / 256u;
       hipLaunchKernelGGL(host_init_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(256), 0, stream,
-                         ht->keys, (u64 *)ht->stats, ht->capacity);
+                         (u64 *)ht->keys, (u64 *)ht->stats, ht->capacity);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "host table init launch");
@@ -1279,9 +1289,9 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   // slots in use, counted after the classify launch (and on an empty run)
   auto count_hosts = [&]() -> int {
     if (!ht) return GNM_OK;
-    const uint64_t cap = (uint64_t)device_cus(dev) * 16u, blocks = (ht->capacity + 255u) / 256u;
+    const uint64_t cap = (uint64_t)device_cus(dev) * 2u, blocks = (ht->capacity + 255u) / 256u;
     hipLaunchKernelGGL(host_count_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(256), 0, stream,
-                       (const uint64_t *)ht->keys, ht->capacity, (u64 *)ht->counters);
+                       (const u64 *)ht->keys, ht->capacity, (u64 *)ht->counters);
     const hipError_t e2 = hipGetLastError();
     return e2 == hipSuccess ? GNM_OK : hip_fail(e2, "host count launch");
   };
@@ -1302,7 +1312,7 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   a.hist = p.rate_hist;
   a.hist_rows = 2u * reg->n_sites;
   if (ht) {
-    a.host_keys = ht->keys;
+    a.host_keys = (u64 *)ht->keys;
     a.host_stats = (u64 *)ht->stats;
     a.host_mask = ht->capacity - 1u;
     a.host_counters = (u64 *)ht->counters;
