@@ -139,7 +139,8 @@ typedef struct {
   uint64_t *stats;    /* DEVICE [capacity * 5], 8-byte aligned */
   uint64_t capacity;  /* a power of two, at most 2^36 */
   uint64_t *counters; /* DEVICE [2]: [0] slots in use after the call; [1] bulk flows left out because
-                         every slot was taken by other hosts (their hosts are then absent) */
+                         the 256 slots from their key's hash position were taken by other hosts
+                         (their hosts are then absent; a host present has all its flows) */
 } gnm_host_table;
 
 /* Per-call parameters.  Zero-initialise and set what you need;
@@ -317,7 +318,8 @@ int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
  *                   flagged means floor(rate_sum_bps / bulk_flows) <
  *                   threshold_bps (strict).  The "no site" and NODIR rows are
  *                   never flagged.
- * Errors: GNM_E_INVAL (null pointers, n_windows = 0), GNM_E_HIP.
+ * Errors: GNM_E_INVAL (null pointers, n_windows = 0, a registry of another
+ * device), GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP.
  */
 int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_windows,
                         uint64_t threshold_bps, uint64_t min_bulk_flows, uint8_t *flags,
@@ -350,8 +352,9 @@ int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_
  *                   before it (the warning).
  * Enqueues two kernels: the medians and low bits (one workgroup per
  * (window, site), reading each histogram once), then the two-window rule
- * (one lane per site).  Errors: GNM_E_INVAL (null pointers, n_windows = 0),
- * GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP.
+ * (one lane per site).  Errors: GNM_E_INVAL (null pointers, n_windows = 0,
+ * a registry of another device), GNM_E_UNSUPPORTED (host-only registry),
+ * GNM_E_HIP.
  */
 int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hist, uint32_t n_windows,
                      uint64_t threshold_bps, uint64_t min_bulk_flows, const uint8_t *prev_flags,

@@ -61,6 +61,7 @@ constexpr uint32_t kFeatHist = 1;         // classify_kernel FEAT bits: rate his
 constexpr uint32_t kFeatHosts = 2;        //   per-host statistics
 constexpr uint64_t kHostEmpty = ~0ull;    // free slot of the host table
 constexpr uint32_t kHostFields = 5;       // host statistics: bulk flows, bytes, rate sum, min, max
+constexpr uint32_t kHostMaxProbes = 256;  // slots a flow tries from its hash position
 constexpr uint32_t kHistKeyBits = 14;     // LDS histogram cache key: row << 14 | bucket
 constexpr uint32_t kHistSlotsMax = 4096;  // LDS histogram cache slots (8 bytes each, 4-way sets)
 constexpr uint32_t kMedWaves = 4;         // median kernel: one wave per (window, site), 4 per workgroup
@@ -653,13 +654,17 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 // the key array).  A slot's key is claimed with a device-scope
 // compare-and-swap and never changes afterwards, so a non-empty key read with
 // a plain load is current; an empty one may be stale, which the
-// compare-and-swap settles.  When every slot is taken by other hosts the flow
-// is counted as left out.  (Keys and statistics in one 64-byte slot measured
+// compare-and-swap settles.  When the 256 slots from the key's hash position
+// are all taken by other hosts the flow is counted as left out (slots are
+// never freed, so the host's later flows are left out too, and a host in the
+// table has all its flows).  The bound keeps a full table from costing a
+// walk over every slot per flow.  (Keys and statistics in one 64-byte slot measured
 // the same here and cost more to clear and count: the six device-scope
 // operations per flow set the pace.)
 __device__ __forceinline__ void host_add(const ClassifyArgs &a, uint64_t key, uint64_t bytes, uint64_t rate) {
   uint64_t h = mix64(key) & a.host_mask;
-  for (uint64_t probe = 0; probe <= a.host_mask; ++probe) {
+  const uint64_t probes = a.host_mask < kHostMaxProbes ? a.host_mask + 1u : kHostMaxProbes;
+  for (uint64_t probe = 0; probe < probes; ++probe) {
     uint64_t cur = a.host_keys[h];
     if (cur == kHostEmpty) cur = atomicCAS(&a.host_keys[h], (u64)kHostEmpty, (u64)key);
     if (cur == kHostEmpty || cur == key) {
@@ -1366,6 +1371,10 @@ extern "C" int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, 
   if (!reg || !acc || !flags) { set_last_error("NULL argument"); return GNM_E_INVAL; }
   if (reg->host_only) { set_last_error("registry was built host-only"); return GNM_E_UNSUPPORTED; }
   if (n_windows == 0) { set_last_error("n_windows must be >= 1"); return GNM_E_INVAL; }
+  int dev = -1;
+  hipError_t e0 = hipGetDevice(&dev);
+  if (e0 != hipSuccess) return hip_fail(e0, "hipGetDevice");
+  if (dev != reg->device) { set_last_error("registry belongs to another device"); return GNM_E_INVAL; }
   const uint64_t items = (uint64_t)n_windows * reg->n_sites;
   const uint64_t need = min_bulk_flows > 1 ? min_bulk_flows : 1;
   const uint64_t blocks = (items + 255) / 256;
@@ -1385,6 +1394,7 @@ extern "C" int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hi
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != reg->device) { set_last_error("registry belongs to another device"); return GNM_E_INVAL; }
   const uint64_t items = (uint64_t)n_windows * reg->n_sites;
   const uint64_t cap = (uint64_t)device_cus(dev) * 64u;
   const uint64_t blocks = (items + kMedWaves - 1u) / kMedWaves;
