@@ -451,23 +451,23 @@ uint64_t gnm_netflow_v5_workspace_bytes(uint64_t n_datagrams);
 /*
  * gnm_netflow_v5_decode — decode datagrams stored back to back.
  *   datagrams       DEVICE buffer of buf_bytes bytes, 4-byte aligned.
- *   offsets         DEVICE array of n_datagrams+1 uint64: datagram d spans
- *                   [offsets[d], offsets[d+1]).
+ *   offsets         DEVICE array of n_datagrams+1 uint64 (8-byte aligned):
+ *                   datagram d spans [offsets[d], offsets[d+1]).
  *   workspace       DEVICE scratch of gnm_netflow_v5_workspace_bytes(n)
  *                   bytes, 256-byte aligned, caller-owned (contents do not
  *                   matter; calls in flight must not share one).
  *   out             output arrays; record j of the accepted datagrams, in
  *                   datagram order, goes to index j if j < out->capacity
  *                   (later records are dropped).
- *   n_records       DEVICE uint64: records the accepted datagrams carry
- *                   (may exceed out->capacity).
- *   n_rejected      DEVICE uint64: datagrams rejected.
+ *   n_records       DEVICE uint64 (8-byte aligned): records the accepted
+ *                   datagrams carry (may exceed out->capacity).
+ *   n_rejected      DEVICE uint64 (8-byte aligned): datagrams rejected.
  * A datagram is accepted when its span lies in the buffer, starts at a
  * multiple of 4, holds the header, carries version 5 and a count of 1..30,
  * and holds count records (bytes after them are ignored).  Enqueues five
  * kernels on `stream` (count, three scan passes, decode).  Errors:
- * GNM_E_INVAL (null pointers, misaligned buffer or workspace, workspace too
- * small, more than 2^31 datagrams), GNM_E_HIP.
+ * GNM_E_INVAL (null pointers, misaligned buffer, offsets, counters or
+ * workspace, workspace too small, more than 2^31 datagrams), GNM_E_HIP.
  */
 int gnm_netflow_v5_decode(const uint8_t *datagrams, uint64_t buf_bytes, const uint64_t *offsets,
                           uint64_t n_datagrams, void *workspace, uint64_t workspace_bytes,

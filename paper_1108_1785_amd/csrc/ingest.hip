@@ -234,6 +234,10 @@ extern "C" int gnm_netflow_v5_decode(const uint8_t *datagrams, uint64_t buf_byte
   }
   if (n_datagrams > 0 && !datagrams) { set_last_error("NULL datagram buffer"); return GNM_E_INVAL; }
   if ((uintptr_t)datagrams & 3u) { set_last_error("datagram buffer not 4-byte aligned"); return GNM_E_INVAL; }
+  if (((uintptr_t)offsets | (uintptr_t)n_records | (uintptr_t)n_rejected) & 7u) {
+    set_last_error("offsets or counters not 8-byte aligned");
+    return GNM_E_INVAL;
+  }
   if (n_datagrams > (1ull << 31)) { set_last_error("more than 2^31 datagrams"); return GNM_E_INVAL; }
   if (!out->src_ip || !out->dst_ip || !out->bytes || !out->packets || !out->first_ms || !out->last_ms) {
     set_last_error("NULL output field");

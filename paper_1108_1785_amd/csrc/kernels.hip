@@ -64,7 +64,7 @@ constexpr uint32_t kHostFields = 5;       // host statistics: bulk flows, bytes,
 constexpr uint32_t kHostMaxProbes = 256;  // slots a flow tries from its hash position
 constexpr uint32_t kHistKeyBits = 14;     // LDS histogram cache key: row << 14 | bucket
 constexpr uint32_t kHistSlotsMax = 4096;  // LDS histogram cache slots (8 bytes each, 4-way sets)
-constexpr uint32_t kMedWaves = 4;         // median kernel: one wave per (window, site), 4 per workgroup
+constexpr uint32_t kMedWaves = 4;         // median kernel: waves sharing one (window, site) item
 constexpr uint32_t kMedRun = 16;          // buckets per lane per batch: 64 * 16 = 1024 per batch
 constexpr uint32_t kMedBatchWords = 64u * kMedRun;
 constexpr uint32_t kMedBatches = (kBuckets + kMedBatchWords - 1u) / kMedBatchWords;  // 5
@@ -1055,46 +1055,53 @@ __device__ __forceinline__ void batch_sums(const uint32_t *r0, const uint32_t *r
   }
 }
 
-// Lower medians of the rate histograms: one wave per (window, site) item, the
-// item's two rows (inbound, outbound) side by side.  A first pass streams
-// both rows once, keeping each 1024-bucket batch's total; the second re-reads
-// only the batch that holds the median.  Writes the median buckets (NO_MEDIAN when a row has no
+// Lower medians of the rate histograms: one workgroup of 4 waves per (window,
+// site) item.  The waves share the item's two rows (inbound, outbound): each
+// streams every 4th 1024-bucket batch of both rows once (32 loads in flight
+// per lane) and leaves the batch totals in LDS; then wave d walks row d from
+// those totals, re-reading only the batch that holds the median.  (One wave
+// per item left a single window's 1,000 items too few waves to cover the
+// memory latency.)  Writes the median buckets (NO_MEDIAN when a row has no
 // bulk flow) when `median` is not NULL, and bits 0/1 of the item's flag
 // byte: total >= need and bucket * 10 kbps < threshold.
 __global__ __launch_bounds__(64 * kMedWaves) void median_kernel(const uint32_t *__restrict__ hist, uint64_t items,
                                                                uint64_t threshold, uint64_t need,
                                                                uint32_t *__restrict__ median,
                                                                uint8_t *__restrict__ flags) {
+  __shared__ u64 s_bsum[2][kMedBatches];
+  __shared__ uint32_t s_med[2];
+  __shared__ u64 s_total[2];
   const uint32_t lane = threadIdx.x % 64u, wave = threadIdx.x / 64u;
-  for (uint64_t item = (uint64_t)blockIdx.x * kMedWaves + wave; item < items;
-       item += (uint64_t)gridDim.x * kMedWaves) {
+  for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
     const uint32_t *r0 = hist + 2u * item * kBuckets, *r1 = r0 + kBuckets;
-    u64 bs0 = 0, bs1 = 0, t0 = 0, t1 = 0;
 #pragma unroll 1
-    for (uint32_t b = 0; b < kMedBatches; ++b) {
+    for (uint32_t b = wave; b < kMedBatches; b += kMedWaves) {
       u64 s0, s1;
       batch_sums(r0, r1, b, lane, s0, s1);
       s0 = wave_sum(s0);
       s1 = wave_sum(s1);
-      if (lane == b) { bs0 = s0; bs1 = s1; }
-      t0 += s0;
-      t1 += s1;
-    }
-    uint32_t m0 = 0, m1 = 0;
-#pragma unroll 1
-    for (uint32_t d = 0; d < 2; ++d) {
-      const uint32_t m = row_median(d ? r1 : r0, d ? bs1 : bs0, d ? t1 : t0, lane);
-      if (d) m1 = m;
-      else m0 = m;
-    }
-    if (lane == 0u) {
-      if (median) {
-        median[2u * item] = m0;
-        median[2u * item + 1u] = m1;
+      if (lane == 0u) {
+        s_bsum[0][b] = s0;
+        s_bsum[1][b] = s1;
       }
+    }
+    __syncthreads();
+    if (wave < 2u) {
+      const u64 bs = lane < kMedBatches ? s_bsum[wave][lane] : 0u;
+      const u64 total = wave_sum(bs);
+      const uint32_t m = row_median(wave ? r1 : r0, bs, total, lane);
+      if (lane == 0u) {
+        s_med[wave] = m;
+        s_total[wave] = total;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0u) {
       uint8_t f = 0;
-      if (t0 >= need && (u64)m0 * kBucketBps < threshold) f |= 1u;
-      if (t1 >= need && (u64)m1 * kBucketBps < threshold) f |= 2u;
+      for (uint32_t d = 0; d < 2; ++d) {
+        if (median) median[2u * item + d] = s_med[d];
+        if (s_total[d] >= need && (u64)s_med[d] * kBucketBps < threshold) f |= (uint8_t)(1u << d);
+      }
       flags[item] = f;
     }
   }
@@ -1396,8 +1403,8 @@ extern "C" int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hi
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != reg->device) { set_last_error("registry belongs to another device"); return GNM_E_INVAL; }
   const uint64_t items = (uint64_t)n_windows * reg->n_sites;
-  const uint64_t cap = (uint64_t)device_cus(dev) * 64u;
-  const uint64_t blocks = (items + kMedWaves - 1u) / kMedWaves;
+  const uint64_t cap = (uint64_t)device_cus(dev) * 16u;
+  const uint64_t blocks = items;
   const uint64_t need = min_bulk_flows > 1 ? min_bulk_flows : 1;
   hipLaunchKernelGGL(median_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(64 * kMedWaves), 0, stream,
                      rate_hist, items, threshold_bps, need, median_bucket, flags);
