@@ -210,3 +210,26 @@ def test_filter_params_checked():
     with pytest.raises(ValueError):
         gnm.make_params(filters={"max_packets": 1})
     assert set(gnm.FILTER_KEYS) == set(oracle.FILTER_KEYS)
+
+
+def test_new_binding_arguments_checked_on_the_host():
+    with pytest.raises(ValueError):
+        gnm.HostTable(1000)            # not a power of two, rejected before any allocation
+    with pytest.raises(ValueError):
+        gnm.make_params(hosts=object())
+    with pytest.raises(ValueError):
+        gnm.make_params(filters={"min_packets": -1})
+    assert gnm.RATE_BUCKETS == 10001 and gnm.RATE_BUCKET_BPS == 10_000
+    assert gnm.RATE_BUCKETS == oracle.RATE_BUCKETS and gnm.NO_MEDIAN == oracle.NO_MEDIAN
+    # the workspace of the v5 decode grows with the datagram count, from a fixed floor
+    w0, w1 = gnm.netflow_v5_workspace_bytes(0), gnm.netflow_v5_workspace_bytes(1000)
+    assert w0 > 0 and w1 >= w0 + 1000 * 12
+
+
+def test_gnm_params_layout_matches_header():
+    # the binding's structure must match the C one field for field: the library
+    # fills the defaults through it
+    p = gnm.lib().gnm_params_default()
+    assert p.bulk_bytes == 1_000_000 and p.flags == 0 and not p.rate_hist and not p.hosts
+    assert (p.min_avg_packet_bytes, p.min_packets, p.min_duration_ms) == (0, 0, 0)
+    assert ctypes.sizeof(gnm.Params) == 8 + 4 * 4 + 8 + 8 + 8 + 4 * 4 + 8
