@@ -45,6 +45,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -68,11 +69,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_only(text: str) -> str:
+    """C++ source without comments or blank space, so that edits to comments
+    do not mark measured counters as stale (the compiled code is the same)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("kernels.hip", "gnm_internal.h"):
-        with open(os.path.join(ROOT, "paper_1108_1785_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1108_1785_amd", "csrc", f)) as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -640,7 +640,6 @@ __device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyAr
   for (int k = 0; k < R; ++k) row[k] = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
 }
 
-// Aggregate the tile's classified records.
 // Finalizer of splitmix64: spreads the host keys over the table.
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   x ^= x >> 30;
@@ -687,6 +686,7 @@ __device__ __forceinline__ uint32_t rate_bucket(uint64_t rate) {
   return rate >= kTop ? kBuckets - 1u : (uint32_t)rate / kBucketBps;
 }
 
+// Aggregate the tile's classified records.
 template <int R, bool ACC_LDS, uint32_t FEAT>
 __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t (&row)[R], const Rest<R> &r,
                                                const ClassifyArgs &a, const Lds &L, u64 *g_tab,
