@@ -173,6 +173,28 @@ class GpuExecutor:
             ev.record(self.copy_stream)
         return ev
 
+    def start_copy_group(self, reqs: List[Request]) -> None:
+        """Stage requests that were admitted together and sit back to back in the
+        arena.  Device-resident records go in with one concatenating copy per
+        field for the whole group (one event for all of them), rather than a
+        copy per field and window; host records keep their own copies."""
+        torch = self.torch
+        live = [r for r in reqs if r.n]
+        on_device = all(getattr(r.records[f], "is_cuda", False) for r in live for f in RECORD_FIELDS)
+        contiguous = all(b.offset == a.offset + a.n for a, b in zip(live, live[1:]))
+        if len(live) < 2 or not on_device or not contiguous:
+            for r in reqs:
+                r.copy_event = self.start_copy(r)
+            return
+        lo, hi = live[0].offset, live[-1].offset + live[-1].n
+        with torch.cuda.stream(self.copy_stream):
+            for f in RECORD_FIELDS:
+                torch.cat([r.records[f][:r.n] for r in live], out=self.buf[f][lo:hi])
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        for r in reqs:
+            r.copy_event = ev if r.n else None
+
     @staticmethod
     def done(event) -> bool:
         return event is None or event.query()
@@ -274,21 +296,38 @@ class Server:
 
     # ------------------------------------------------------------ scheduler
     def _admit(self) -> bool:
-        progressed = False
+        # admit what the arena can take now, then stage it: runs of windows
+        # that landed back to back are staged together
+        group: List[Request] = []
         while True:
             with self.lock:
                 if not self.waiting:
-                    return progressed
+                    break
                 req = self.waiting[0]
                 off = self._alloc(req)
                 if off is None:
                     self.stats["admission_waits"] += 1
-                    return progressed
+                    break
                 self.waiting.popleft()
             req.offset = off
-            req.copy_event = self.ex.start_copy(req)
-            self.copying.append(req)
-            progressed = True
+            group.append(req)
+        if not group:
+            return False
+        stage = getattr(self.ex, "start_copy_group", None)
+        run: List[Request] = []
+        for req in group + [None]:
+            if req is not None and (not run or not req.n or not run[-1].n or
+                                    req.offset == run[-1].offset + run[-1].n):
+                run.append(req)
+                continue
+            self.copying.extend(run)  # pending before staging: a failure fails them too
+            if stage is not None:
+                stage(run)
+            else:
+                for r in run:
+                    r.copy_event = self.ex.start_copy(r)
+            run = [req] if req is not None else []
+        return True
 
     def _alloc(self, req: Request) -> Optional[int]:
         # empty windows take no arena space and sit at the current head

@@ -132,3 +132,27 @@ def test_served_device_resident_records(small):
     for w, r in zip(wins, res):
         acc, fl = _expect(orc, reg_h.n_sites, w)
         assert (r.acc == acc).all() and (r.flags == fl).all()
+
+
+def test_served_device_resident_burst_grouped_staging(small):
+    """A burst of device-resident windows, empty ones among them, through an
+    arena small enough to wrap and push back: windows admitted together are
+    staged with one concatenating copy per field; each result still equals the
+    oracle of its window."""
+    from tests._gpu import to_device
+    reg_h, reg, orc, pool = small
+    rng = np.random.default_rng(21)
+    sizes = [0 if rng.random() < 0.15 else int(rng.integers(1, 20_000)) for _ in range(60)]
+    wins = _windows(pool, sizes, 22)
+    dev = [to_device(w) for w in wins]
+    srv = _server(reg, capacity=64_000, max_w=16, inflight=2)
+    try:
+        futs = [srv.submit(d, n=w.n) for d, w in zip(dev, wins)]
+        res = [f.result(timeout=120) for f in futs]
+        stats = dict(srv.stats)
+    finally:
+        srv.close()
+    for w, r in zip(wins, res):
+        acc, fl = _expect(orc, reg_h.n_sites, w)
+        assert (r.acc == acc).all() and (r.flags == fl).all()
+    assert stats["admission_waits"] > 0 and stats["launches"] < 60
