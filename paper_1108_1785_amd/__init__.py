@@ -154,7 +154,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libgnm.so is not built (run __graft_entry__.build()); "
+            raise RuntimeError("libgnm.so is not built (run python -m paper_1108_1785_amd._build); "
                                "there is no non-HIP implementation of this path")
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
