@@ -178,3 +178,19 @@ def test_hosts_bad_capacity_rejected(torch_cuda):
     assert e.value.code == -1
     with pytest.raises(ValueError):
         gnm.HostTable(1000, device=DEV)
+
+
+def test_hosts_no_records(torch_cuda):
+    import torch
+    say("case: hosts with no records")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    t = gnm.HostTable(256, device=DEV)
+    t.keys.fill_(5)
+    t.counters.fill_(9)
+    acc = torch.empty((1, reg.rows, 8), dtype=torch.int64, device=DEV)
+    empty = to_device(s["rec"].slice(0, 0))
+    gnm.classify_aggregate(reg, empty, acc, n=0, hosts=t)
+    torch.cuda.synchronize()
+    keys, st, used, dropped = t.to_numpy()
+    assert keys.size == 0 and used == 0 and dropped == 0

@@ -261,3 +261,20 @@ def test_median_hist_alignment_rejected(torch_cuda):
     with pytest.raises(gnm.GnmError) as e:
         gnm.classify_aggregate(reg, to_device(rec), acc, n=rec.n, rate_hist=h[1:])
     assert e.value.code == -1
+
+
+def test_median_empty_windows(torch_cuda):
+    """Empty windows have all-zero histograms, no medians and no low bits; the
+    warning chain passes through them (an empty window breaks a run)."""
+    say("case: median with empty windows")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"]
+    off = np.array([0, 0, 0, 30_000, 30_000, 60_000, rec.n, rec.n], dtype=np.uint64)
+    prev = np.full(s["reg"].n_sites, 3, dtype=np.uint8)
+    exp = oracle_median(s["orc"], rec, off, prev=prev)
+    for grid in (0, 7):
+        got = gpu_median(reg, rec, off, prev=prev, grid_blocks=grid)
+        check(got, exp, grid)
+    assert (got[0][[0, 1, 3, 6]] == 0).all() and (got[1][[0, 1, 3, 6]] == oracle.NO_MEDIAN).all()
+    assert (got[2][[0, 1, 3, 6]] == 0).all()
