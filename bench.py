@@ -119,6 +119,17 @@ def generate(jobs, workers):
         return list(ex.map(_gen, jobs))
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
 
@@ -628,7 +639,8 @@ def main():
         forms["served_device_resident"] = svr
         # saturation: a burst of windows at once, from device memory; the
         # request loop batches whatever has arrived whenever a launch slot frees
-        sat, _, _, _ = served_run(gnm, serve, reg1, pool_dev, pool.n, 0.0, 0.0, flowgen.SEED_BASE + 402,
+        sat, sat_res, sat_offs, sat_sizes = served_run(gnm, serve, reg1, pool_dev, pool.n, 0.0, 0.0,
+                                                       flowgen.SEED_BASE + 402,
                                   resident=True, burst=2000)
         log("served (burst of 2000): %.3g records/s, %.1f windows/launch, p50 %.1f ms p99 %.1f ms" %
             (sat["records_per_s"], sat["windows_per_launch"], sat["latency_ms_p50"], sat["latency_ms_p99"]))
@@ -645,7 +657,9 @@ def main():
     parity = "not checked (--no-cpu)"
     if not args.no_cpu:
         import oracle
+        t_orc_reg = time.perf_counter()
         orc = oracle.Registry.from_generated(reg_h)
+        t_orc_reg = time.perf_counter() - t_orc_reg
         reps, t_cpu, exp = 0, 0.0, None
         while reps < 400 and (reps == 0 or t_cpu < 10.0):
             tc = time.perf_counter()
@@ -654,9 +668,16 @@ def main():
             reps += 1
             if reps == 1 or reps % 20 == 0:
                 log("oracle rep %d: %.2fs" % (reps, t_cpu))
+        t1 = time.perf_counter()
+        orc.classify_aggregate(parts[0], threads=1)
+        t1 = time.perf_counter() - t1
         cpu = {"value": reps * n_win / t_cpu, "unit": "records/s", "cores": oracle.max_threads(),
                "kind": "oracle",
-               "sample": "%d x one full %d-record plain-large window (OpenMP over records)" % (reps, n_win)}
+               "sample": "%d x one full %d-record plain-large window (OpenMP over records)" % (reps, n_win),
+               "single_thread_records_per_s": n_win / t1, "registry_build_s": t_orc_reg,
+               "cpu_model": host_cpu_model(), "host_cpus_visible": os.cpu_count()}
+        log("oracle: %.3g records/s on %d threads, %.3g on one; registry build %.2fs" %
+            (cpu["value"], cpu["cores"], n_win / t1, t_orc_reg))
         bad = []
         if not (got_plain == exp).all():
             bad.append("plain")
@@ -726,9 +747,11 @@ def main():
                     if not (acc5_h[j] == e).all() or not (flags5_h[j] == oracle.flags(e, reg5_h.n_sites)).all():
                         bad.append("large-table window %d" % w)
                 parity_notes["large_table_windows_checked"] = 2
+            # every served window, offline against the oracle
             for tag, res, offs_, sizes_ in (("served", sv_res, sv_offs, sv_sizes),
-                                            ("served resident", svr_res, svr_offs, svr_sizes)):
-                pick = rs.choice(len(res), min(32, len(res)), replace=False)
+                                            ("served resident", svr_res, svr_offs, svr_sizes),
+                                            ("served burst", sat_res, sat_offs, sat_sizes)):
+                pick = range(len(res))
                 for i in pick:
                     o, n = int(offs_[i]), int(sizes_[i])
                     e = orc1.classify_aggregate(pool.slice(o, o + n))
