@@ -97,3 +97,22 @@ def is_local_np(reg, ips):
         m = 0 if L == 0 else (0xFFFFFFFF << (32 - L)) & 0xFFFFFFFF
         out |= (ips & np.uint64(m)) == np.uint64(a & m)
     return out
+
+
+def median_example():
+    """The hand-worked median example: (sites, local, n_sites, records, offsets, golden dict)."""
+    g = load_golden("median_example.json")
+    sites = [(ip(a), l, s) for a, l, s in g["sites"]]
+    local = [(ip(a), l) for a, l in g["local"]]
+    recs = [(ip(r[0]), ip(r[1]), r[2], r[3], r[4], r[5]) for r in g["records"]]
+    off = np.array(g["window_offsets"], dtype=np.uint64)
+    return sites, local, g["n_sites"], recs, off, g
+
+
+def dense_histograms(g, rows: int) -> np.ndarray:
+    """The golden's sparse (row, bucket, count) lists as uint32[n_windows, rows, 10001]."""
+    out = np.zeros((len(g["expected_histograms"]), rows, 10001), dtype=np.uint32)
+    for w, entries in enumerate(g["expected_histograms"]):
+        for r, b, c in entries:
+            out[w, r, b] = c
+    return out

@@ -278,3 +278,17 @@ def test_median_empty_windows(torch_cuda):
         check(got, exp, grid)
     assert (got[0][[0, 1, 3, 6]] == 0).all() and (got[1][[0, 1, 3, 6]] == oracle.NO_MEDIAN).all()
     assert (got[2][[0, 1, 3, 6]] == 0).all()
+
+
+def test_median_worked_example_on_gpu(torch_cuda):
+    """The hand-worked example: histograms, lower medians and flags as derived by hand."""
+    from tests._helpers import dense_histograms, median_example
+    say("case: median worked example")
+    sites, local, S, recs, off, g = median_example()
+    reg, _ = _regs(sites, local, S)
+    got = gpu_median(reg, soa(recs), off, bulk_bytes=g["bulk_bytes"], threshold_bps=g["threshold_bps"],
+                     prev=np.array(g["prev_flags"], dtype=np.uint8))
+    assert (got[0] == dense_histograms(g, 2 * S)).all()
+    want = [[gnm.NO_MEDIAN if m == "NONE" else m for m in w] for w in g["expected_medians"]]
+    assert got[1].tolist() == want
+    assert got[2].tolist() == g["expected_flags"]

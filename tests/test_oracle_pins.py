@@ -537,3 +537,20 @@ def test_host_stats_add_up_to_the_site_rows():
     ips = (keys >> np.uint64(32)).astype(np.uint32)
     assert (o.lookup(ips) == (row_of_key // 2).astype(np.uint32)).all()
     assert keys.size > 10_000 and (st[:, 0] > 1).any()
+
+
+def test_median_worked_example():
+    from tests._helpers import dense_histograms, median_example
+    sites, local, S, recs, off, g = median_example()
+    reg = _oracle_reg(sites, local, S)
+    h = oracle.rate_histograms(reg, soa(recs), window_offsets=off, bulk_bytes=g["bulk_bytes"])
+    assert (h[:, :2 * S] == dense_histograms(g, 2 * S)).all()
+    # the oracle also counts the rows the library keeps no histogram for: the
+    # inbound flow from 203.0.113.9 (no registered site) and the both-local one
+    assert h[0, 2 * S].sum() == 1 and h[0, 2 * S + 2].sum() == 1 and h[:, 2 * S:].sum() == 2
+    med, cnt = oracle.rate_medians(reg, soa(recs), window_offsets=off, bulk_bytes=g["bulk_bytes"])
+    want = [[oracle.NO_MEDIAN if m == "NONE" else m for m in w] for w in g["expected_medians"]]
+    assert med[:, :2 * S].tolist() == want
+    assert cnt[:, :2 * S].tolist() == g["expected_counts"]
+    f = oracle.median_flags(med, cnt, S, g["threshold_bps"], 0, np.array(g["prev_flags"], dtype=np.uint8))
+    assert f.tolist() == g["expected_flags"]
