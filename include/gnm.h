@@ -326,6 +326,22 @@ int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_
                         hipStream_t stream);
 
 /*
+ * gnm_classify_flag — one window step of §III.B.1 (NetPerf Monitoring
+ * Thread) over §III.B.2 (TransRate Kernel): gnm_classify_aggregate(reg, rec,
+ * window_offsets, n_windows, p, acc) followed by gnm_flag_suboptimal(reg,
+ * acc, n_windows, threshold_bps, min_bulk_flows, flags), in one call with the
+ * same results bit for bit.  With a usable p->workspace the mean-rate test
+ * runs inside the reduce kernel on the rows it has just combined (no flag
+ * launch); otherwise the flag kernel follows the classify kernel.  Arguments,
+ * layouts and ownership are those of the two calls; flags is a DEVICE array
+ * of n_windows * n_sites bytes.  Errors: those of gnm_classify_aggregate, and
+ * GNM_E_INVAL for a NULL flags.
+ */
+int gnm_classify_flag(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                      uint32_t n_windows, const gnm_params *p, gnm_acc *acc, uint64_t threshold_bps,
+                      uint64_t min_bulk_flows, uint8_t *flags, hipStream_t stream);
+
+/*
  * gnm_median_flags — the paper's warning criterion (§III.B.1, NetPerf
  * Monitoring Thread; §IV.B): a site is warned about when the median of its
  * transfer rates stays below a standard (1 Mbps) for two consecutive windows
@@ -371,9 +387,9 @@ typedef struct gnm_graph gnm_graph; /* opaque */
 
 /*
  * gnm_graph_create — capture one step: gnm_classify_aggregate(reg, rec,
- * window_offsets, n_windows, p, acc) followed, when flags is not NULL, by
- * gnm_flag_suboptimal(reg, acc, n_windows, threshold_bps, min_bulk_flows,
- * flags).  All pointers (records, offsets, acc, flags, p->workspace,
+ * window_offsets, n_windows, p, acc), or, when flags is not NULL,
+ * gnm_classify_flag(reg, rec, window_offsets, n_windows, p, acc,
+ * threshold_bps, min_bulk_flows, flags).  All pointers (records, offsets, acc, flags, p->workspace,
  * p->rate_hist) are
  * baked into the graph: every replay reads and writes those same buffers,
  * whose contents the caller may change between replays.  The call runs the

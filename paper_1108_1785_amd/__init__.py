@@ -37,7 +37,7 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
            "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_classify_aggregate",
-           "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
+           "gnm_classify_flag", "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
            "gnm_netflow_v5_workspace_bytes", "gnm_netflow_v5_decode",
            "gnm_strerror", "gnm_last_error", "gnm_version")
 TUNE_MAX = 16
@@ -176,6 +176,9 @@ def lib():
         L.gnm_classify_aggregate.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32,
                                              ctypes.POINTER(Params), P, P]
         L.gnm_classify_aggregate.restype = ctypes.c_int
+        L.gnm_classify_flag.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32, ctypes.POINTER(Params), P,
+                                        ctypes.c_uint64, ctypes.c_uint64, P, P]
+        L.gnm_classify_flag.restype = ctypes.c_int
         L.gnm_flag_suboptimal.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.gnm_flag_suboptimal.restype = ctypes.c_int
         L.gnm_median_flags.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P, P, P]
@@ -381,6 +384,15 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
     filters: optional exclusion thresholds, e.g. {"min_avg_packet_bytes": 100}.
     hosts: optional HostTable for per-host statistics.
     """
+    c, off, p = _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumulate, records_per_thread,
+                               grid_blocks, n, workspace, rate_hist, filters, hosts)
+    _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
+                                        ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
+                                        _stream_handle(stream)), "gnm_classify_aggregate")
+
+
+def _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumulate, records_per_thread,
+                   grid_blocks, n, workspace, rate_hist, filters, hosts):
     c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
     if acc.element_size() * acc.numel() < n_windows * reg.rows * 64 or not acc.is_cuda:
         raise ValueError("acc must be a device tensor of n_windows * rows * 64 bytes")
@@ -392,9 +404,24 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
     if rate_hist is not None and rate_hist.numel() < rate_hist_words(reg, n_windows):
         raise ValueError("rate_hist must hold n_windows * 2 * n_sites * 10001 counts")
     p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist, filters, hosts)
-    _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
-                                        ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
-                                        _stream_handle(stream)), "gnm_classify_aggregate")
+    return c, off, p
+
+
+def classify_flag(reg: Registry, rec, acc, flags, threshold_bps: int = 1_000_000, min_bulk_flows: int = 0,
+                  window_offsets=None, n_windows: int = 1, bulk_bytes: int = 1_000_000, accumulate: bool = False,
+                  records_per_thread: int = 0, grid_blocks: int = 0, stream=None, n: Optional[int] = None,
+                  workspace=None, rate_hist=None, filters=None, hosts=None) -> None:
+    """gnm_classify_flag: classify_aggregate then flag_suboptimal in one call (the flag
+    test fused into the table merge when a workspace is given); same arguments as
+    those two."""
+    if flags.element_size() != 1 or flags.numel() < n_windows * reg.n_sites or not flags.is_cuda:
+        raise ValueError("flags must be a device uint8 tensor of n_windows * n_sites bytes")
+    c, off, p = _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumulate, records_per_thread,
+                               grid_blocks, n, workspace, rate_hist, filters, hosts)
+    _check(lib().gnm_classify_flag(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
+                                   ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()), int(threshold_bps),
+                                   int(min_bulk_flows), ctypes.c_void_p(flags.data_ptr()),
+                                   _stream_handle(stream)), "gnm_classify_flag")
 
 
 def flag_suboptimal(reg: Registry, acc, n_windows: int, flags, threshold_bps: int = 1_000_000,

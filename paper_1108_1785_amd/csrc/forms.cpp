@@ -1,4 +1,4 @@
-// Batched form: one classify/aggregate step (and its flag step) captured into
+// Batched form: one classify/aggregate step (with its flag step) captured into
 // a HIP graph for replay, and an autotuner that times launch shapes on the
 // caller's data.  Both drive only the C-ABI entry points of kernels.hip.
 //
@@ -45,8 +45,9 @@ extern "C" int gnm_graph_create(const gnm_registry *reg, const gnm_records *rec,
   hipStream_t s = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_err(e, "hipStreamCreate");
-  int rc = gnm_classify_aggregate(reg, rec, window_offsets, n_windows, p, acc, s);
-  if (rc == GNM_OK && flags) rc = gnm_flag_suboptimal(reg, acc, n_windows, threshold_bps, min_bulk_flows, flags, s);
+  int rc = flags ? gnm_classify_flag(reg, rec, window_offsets, n_windows, p, acc, threshold_bps, min_bulk_flows,
+                                     flags, s)
+                : gnm_classify_aggregate(reg, rec, window_offsets, n_windows, p, acc, s);
   if (rc == GNM_OK) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_err(e, "hipStreamSynchronize");
@@ -61,8 +62,9 @@ extern "C" int gnm_graph_create(const gnm_registry *reg, const gnm_records *rec,
     if (e != hipSuccess) rc = hip_err(e, "hipStreamBeginCapture");
   }
   if (rc == GNM_OK) {
-    int rc2 = gnm_classify_aggregate(reg, rec, window_offsets, n_windows, p, acc, s);
-    if (rc2 == GNM_OK && flags) rc2 = gnm_flag_suboptimal(reg, acc, n_windows, threshold_bps, min_bulk_flows, flags, s);
+    int rc2 = flags ? gnm_classify_flag(reg, rec, window_offsets, n_windows, p, acc, threshold_bps, min_bulk_flows,
+                                        flags, s)
+                    : gnm_classify_aggregate(reg, rec, window_offsets, n_windows, p, acc, s);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (rc2 != GNM_OK) rc = rc2;

@@ -52,7 +52,8 @@ typedef __attribute__((address_space(1))) const uint32_t gu32;
 typedef __attribute__((address_space(1))) const uint64_t gu64;
 
 constexpr uint32_t kThreads = 1024;
-constexpr uint32_t kRedWords = 64;   // reduce kernel: table words per workgroup
+constexpr uint32_t kRedRows = 8;     // reduce kernel: table rows (4 sites) per workgroup
+constexpr uint32_t kRedWords = kRedRows * kAccFields;  // reduce kernel: 56 table words, one per lane
 constexpr uint32_t kRedGroups = 16;  // reduce kernel: waves, each summing every 16th slot
 constexpr uint32_t kRedUnroll = 8;   // reduce kernel: slot loads in flight per lane
 constexpr uint32_t kBuckets = 10001;      // rate histogram: 10 kbps buckets, the last for > 100 Mbps
@@ -882,17 +883,29 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   }
 }
 
+// Mean-rate test of gnm_flag_suboptimal, fused into the reduce kernel when a
+// call asks for both: flags[w * n_sites + s] for every window w and site s.
+struct FlagArgs {
+  uint8_t *flags;  // NULL: no flags
+  uint64_t threshold, need;
+  uint32_t n_sites;
+};
+
 // Combine the workgroups' final tables.  The slots whose window is w form a
 // contiguous range (slot windows never decrease).  Workgroup
-// w * word_tiles + x owns 64 consecutive words (tile x) of window w's
-// flattened table (rows of kAccFields words): lane j of each of its 16 waves
-// reads word j of every 16th slot, so each wave load is one contiguous
-// 512-byte run, and the waves' partial results meet in LDS.  Adds into acc, or
-// overwrites it when the classify launch left no other contribution.
-__global__ __launch_bounds__(kRedWords *kRedGroups) void reduce_partials_kernel(
+// w * row_tiles + x owns rows 8x .. 8x + 7 (sites 4x .. 4x + 3) of window w's
+// table, 56 consecutive words of the flattened table (rows of kAccFields
+// words): lane j < 56 of each of its 16 waves reads word j of every 16th slot,
+// so each wave load is one contiguous 448-byte run, and the waves' partial
+// results meet in LDS.  Adds into acc, or overwrites it when the classify
+// launch left no other contribution.  With flags, wave 0 then holds the final
+// bulk-flow counts and rate sums of the tile's rows and applies the mean-rate
+// test to its four sites, reading acc as it stands where no slot belongs to
+// the window.
+__global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
     const u64 *__restrict__ ws, const uint32_t *__restrict__ meta, uint32_t slots, uint32_t rows,
-    u64 *__restrict__ acc, uint32_t word_tiles, uint32_t overwrite) {
-  const uint32_t w = blockIdx.x / word_tiles, tile = blockIdx.x - w * word_tiles;
+    u64 *__restrict__ acc, uint32_t row_tiles, uint32_t overwrite, FlagArgs fl) {
+  const uint32_t w = blockIdx.x / row_tiles, tile = blockIdx.x - w * row_tiles;
   uint32_t b0 = 0, len = slots;  // first slot with meta >= w
   while (len > 0) {
     const uint32_t half = len >> 1;
@@ -906,15 +919,17 @@ __global__ __launch_bounds__(kRedWords *kRedGroups) void reduce_partials_kernel(
     if (meta[b1 + half] <= w) { b1 += half + 1; len -= half + 1; }
     else len = half;
   }
-  if (b0 == b1) return;
-  const uint32_t lane = threadIdx.x % kRedWords, g = threadIdx.x / kRedWords;
+  const bool any = b0 < b1;
+  if (!any && !fl.flags) return;
+  const uint32_t lane = threadIdx.x % 64u, g = threadIdx.x / 64u;
   const uint32_t words = kAccFields * rows;
   const uint32_t i = tile * kRedWords + lane;
-  const uint32_t f = i % kAccFields;
+  const bool mine = lane < kRedWords && i < words;
+  const uint32_t f = lane % kAccFields;  // = i % kAccFields: tiles start on a row
   const bool is_cnt = f == kCnt, is_min = f == kRateMin, is_max = f == kRateMax;
   // x: sum (or min / max) of the word; y: bulk flows, for the packed count word
   u64 xs = 0, y = 0, xmin = ~0ull, xmax = 0;
-  if (i < words) {
+  if (mine) {
     const u64 *p = ws + i;
     // kRedUnroll loads in flight per lane (indexes past the range reload its
     // last slot and are masked), then branch-free combining
@@ -937,11 +952,11 @@ __global__ __launch_bounds__(kRedWords *kRedGroups) void reduce_partials_kernel(
     }
   }
   u64 x = is_min ? xmin : (is_max ? xmax : xs);
-  __shared__ u64 red[kRedGroups][2][kRedWords];
+  __shared__ u64 red[kRedGroups][2][64];
   red[g][0][lane] = x;
   red[g][1][lane] = y;
   __syncthreads();
-  if (g != 0 || i >= words) return;
+  if (g != 0) return;
   for (uint32_t s = 1; s < kRedGroups; ++s) {
     const u64 v = red[s][0][lane];
     if (f == kRateMin) x = v < x ? v : x;
@@ -950,20 +965,48 @@ __global__ __launch_bounds__(kRedWords *kRedGroups) void reduce_partials_kernel(
     y += red[s][1][lane];
   }
   // table word (row, f) -> acc fields: cnt -> flows (0) and bulk flows (4);
-  // bytes, packets, duration -> 1..3; rate sum, min, max -> 5..7
-  const uint32_t r = i / kAccFields;
-  u64 *o = acc + ((uint64_t)w * rows + r) * 8u;
-  const uint32_t of = f == kCnt ? 0u : (f < kRateSum ? f : f + 1u);
-  if (overwrite) {
-    o[of] = x;
-    if (f == kCnt) o[4] = y;
-  } else if (f == kRateMin) {
-    o[of] = x < o[of] ? x : o[of];
-  } else if (f == kRateMax) {
-    o[of] = x > o[of] ? x : o[of];
-  } else {
-    o[of] += x;
-    if (f == kCnt) o[4] += y;
+  // bytes, packets, duration -> 1..3; rate sum, min, max -> 5..7.  fx, fy:
+  // the word's final value, and the bulk flows beside a count word.
+  u64 fx = 0, fy = 0;
+  if (mine) {
+    const uint32_t r = i / kAccFields;
+    u64 *o = acc + ((uint64_t)w * rows + r) * 8u;
+    const uint32_t of = f == kCnt ? 0u : (f < kRateSum ? f : f + 1u);
+    if (!any) {
+      fx = o[of];
+      fy = f == kCnt ? o[4] : 0ull;
+    } else if (overwrite) {
+      fx = x;
+      fy = y;
+    } else if (f == kRateMin) {
+      const u64 c = o[of];
+      fx = x < c ? x : c;
+    } else if (f == kRateMax) {
+      const u64 c = o[of];
+      fx = x > c ? x : c;
+    } else {
+      fx = o[of] + x;
+      fy = f == kCnt ? o[4] + y : 0ull;
+    }
+    if (any) {
+      o[of] = fx;
+      if (f == kCnt) o[4] = fy;
+    }
+  }
+  if (!fl.flags) return;
+  // lane j < 4 tests site 4 * tile + j: rows 2j (inbound) and 2j + 1
+  // (outbound) of the tile; every lane takes part in the exchanges
+  const uint32_t j = lane & 3u;
+  const uint32_t c0 = 2u * j * kAccFields;
+  const u64 nb0 = __shfl(fy, (int)(c0 + kCnt), 64), sum0 = __shfl(fx, (int)(c0 + kRateSum), 64);
+  const u64 nb1 = __shfl(fy, (int)(c0 + kAccFields + kCnt), 64);
+  const u64 sum1 = __shfl(fx, (int)(c0 + kAccFields + kRateSum), 64);
+  const uint32_t site = tile * (kRedRows / 2u) + j;
+  if (lane < 4u && site < fl.n_sites) {
+    uint8_t fv = 0;
+    if (nb0 >= fl.need && sum0 / nb0 < fl.threshold) fv |= 1u;
+    if (nb1 >= fl.need && sum1 / nb1 < fl.threshold) fv |= 2u;
+    fl.flags[(uint64_t)w * fl.n_sites + site] = fv;
   }
 }
 
@@ -1219,9 +1262,14 @@ extern "C" uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_b
   return partial_bytes(reg, grid);
 }
 
-extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
-                                      const uint64_t *window_offsets, uint32_t n_windows,
-                                      const gnm_params *pp, gnm_acc *acc, hipStream_t stream) {
+namespace {
+
+// gnm_classify_aggregate, and with fl.flags also gnm_flag_suboptimal on the
+// result: fused into the reduce kernel when the workspace is used, otherwise
+// the flag kernel after the classify launch.
+int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                  uint32_t n_windows, const gnm_params *pp, gnm_acc *acc, const FlagArgs &fl,
+                  hipStream_t stream) {
   if (!reg || !rec || !acc) { set_last_error("NULL argument"); return GNM_E_INVAL; }
   if (reg->host_only) { set_last_error("registry was built host-only"); return GNM_E_UNSUPPORTED; }
   if (n_windows == 0) { set_last_error("n_windows must be >= 1"); return GNM_E_INVAL; }
@@ -1261,10 +1309,10 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     set_last_error("host table: NULL or misaligned arrays, or a capacity that is not a power of two up to 2^36");
     return GNM_E_INVAL;
   }
-  const uint64_t word_tiles = (kAccFields * rows + kRedWords - 1) / kRedWords;
+  const uint64_t row_tiles = (rows + kRedRows - 1) / kRedRows;
   const bool use_ws = rec->n > 0 && reg->acc_in_lds && p.workspace &&
                       p.workspace_bytes >= partial_bytes(reg, grid) && aligned16(p.workspace) &&
-                      word_tiles * n_windows <= (uint64_t)INT32_MAX;
+                      row_tiles * n_windows <= (uint64_t)INT32_MAX;
   // With one window, a workspace, no accumulation and slices short enough to
   // need no mid-launch flush, the reduce kernel writes every row of the
   // table, so it needs no initialisation.
@@ -1307,7 +1355,19 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
     const hipError_t e2 = hipGetLastError();
     return e2 == hipSuccess ? GNM_OK : hip_fail(e2, "host count launch");
   };
-  if (rec->n == 0) return count_hosts();
+  // the mean-rate flags, when the reduce kernel does not apply them
+  auto flag_launch = [&]() -> int {
+    if (!fl.flags) return GNM_OK;
+    const uint64_t items = (uint64_t)n_windows * reg->n_sites;
+    hipLaunchKernelGGL(flag_kernel, dim3((uint32_t)((items + 255) / 256)), dim3(256), 0, stream, (const u64 *)acc,
+                       n_windows, reg->n_sites, (uint32_t)rows, fl.threshold, fl.need, fl.flags);
+    const hipError_t e2 = hipGetLastError();
+    return e2 == hipSuccess ? GNM_OK : hip_fail(e2, "flag launch");
+  };
+  if (rec->n == 0) {
+    const int rc = flag_launch();
+    return rc == GNM_OK ? count_hosts() : rc;
+  }
 
   ClassifyArgs a{};
   a.src = rec->src_ip; a.dst = rec->dst_ip; a.bytes = rec->bytes; a.packets = rec->packets;
@@ -1363,13 +1423,33 @@ extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
   if (use_ws) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(word_tiles * n_windows)),
-                       dim3(kRedWords * kRedGroups), 0, stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta,
-                       (uint32_t)grid, (uint32_t)rows, (u64 *)acc, (uint32_t)word_tiles, overwrite ? 1u : 0u);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(row_tiles * n_windows)), dim3(64 * kRedGroups), 0,
+                       stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta, (uint32_t)grid, (uint32_t)rows,
+                       (u64 *)acc, (uint32_t)row_tiles, overwrite ? 1u : 0u, fl);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  } else {
+    const int rc = flag_launch();
+    if (rc != GNM_OK) return rc;
   }
   return count_hosts();
+}
+
+}  // namespace
+
+extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
+                                      const uint64_t *window_offsets, uint32_t n_windows,
+                                      const gnm_params *pp, gnm_acc *acc, hipStream_t stream) {
+  return classify_impl(reg, rec, window_offsets, n_windows, pp, acc, FlagArgs{}, stream);
+}
+
+extern "C" int gnm_classify_flag(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                                 uint32_t n_windows, const gnm_params *p, gnm_acc *acc, uint64_t threshold_bps,
+                                 uint64_t min_bulk_flows, uint8_t *flags, hipStream_t stream) {
+  if (!flags) { set_last_error("NULL argument"); return GNM_E_INVAL; }
+  if (!reg) { set_last_error("NULL argument"); return GNM_E_INVAL; }
+  const FlagArgs fl{flags, threshold_bps, min_bulk_flows > 1 ? min_bulk_flows : 1, reg->n_sites};
+  return classify_impl(reg, rec, window_offsets, n_windows, p, acc, fl, stream);
 }
 
 extern "C" int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_windows,

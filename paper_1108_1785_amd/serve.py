@@ -11,8 +11,9 @@ Monitoring Thread).  Here windows arrive at any time:
   earlier windows are being classified on the compute stream;
 * continuous batching — whenever fewer than `max_inflight` launches are
   running, every admitted window whose copy has finished, consecutive in the
-  arena, goes into one persistent classify launch (gnm_classify_aggregate
-  with window offsets), followed by the flag step;
+  arena, goes into one persistent classify launch (gnm_classify_flag with
+  window offsets: the classify launch, then the table merge with the flag
+  test);
 * isolation — every window has its own accumulator rows, so a window's result
   is the same alone and in any mix.
 
@@ -207,7 +208,7 @@ class GpuExecutor:
 
     def launch(self, slot: int, batch: List[Request]) -> None:
         """One persistent classify launch over consecutive arena windows, then flags and D2H."""
-        from . import classify_aggregate, flag_suboptimal, records_struct
+        from . import classify_flag, records_struct
         torch = self.torch
         s = self.slots[slot]
         base = batch[0].offset
@@ -224,9 +225,9 @@ class GpuExecutor:
             s["off_dev"][:nw + 1].copy_(s["off_host"][:nw + 1], non_blocking=True)
             view = {f: self.buf[f][base:base + max(total, 1)] for f in RECORD_FIELDS}
             rec = records_struct(view, total)
-            classify_aggregate(self.reg, rec, s["acc"], window_offsets=s["off_dev"], n_windows=nw,
-                               bulk_bytes=self.bulk_bytes, workspace=s["ws"], stream=st)
-            flag_suboptimal(self.reg, s["acc"], nw, s["flags"], self.threshold, self.min_bulk, stream=st)
+            classify_flag(self.reg, rec, s["acc"], s["flags"], self.threshold, self.min_bulk,
+                          window_offsets=s["off_dev"], n_windows=nw, bulk_bytes=self.bulk_bytes,
+                          workspace=s["ws"], stream=st)
             s["acc_host"][:nw].copy_(s["acc"][:nw], non_blocking=True)
             s["flags_host"][:nw * self.n_sites].copy_(s["flags"][:nw * self.n_sites], non_blocking=True)
             ev = torch.cuda.Event()

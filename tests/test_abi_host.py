@@ -155,6 +155,14 @@ def test_device_calls_reject_host_only_registry_and_nulls():
     assert rc == gnm.GNM_E_UNSUPPORTED
     assert L.gnm_classify_aggregate(None, ctypes.byref(rec), None, 1, None, ctypes.c_void_p(8), None) == gnm.GNM_E_INVAL
     assert L.gnm_flag_suboptimal(None, None, 1, 1, 0, None, None) == gnm.GNM_E_INVAL
+    rc = L.gnm_classify_flag(reg.handle, ctypes.byref(rec), None, 1, ctypes.byref(p), ctypes.c_void_p(8), 10, 0,
+                             ctypes.c_void_p(8), None)
+    assert rc == gnm.GNM_E_UNSUPPORTED
+    rc = L.gnm_classify_flag(reg.handle, ctypes.byref(rec), None, 1, ctypes.byref(p), ctypes.c_void_p(8), 10, 0,
+                             None, None)
+    assert rc == gnm.GNM_E_INVAL
+    assert L.gnm_classify_flag(None, ctypes.byref(rec), None, 1, None, ctypes.c_void_p(8), 10, 0,
+                               ctypes.c_void_p(8), None) == gnm.GNM_E_INVAL
     assert L.gnm_acc_rows(None) == 0
     assert L.gnm_registry_free(None) == 0
     reg.close()
