@@ -60,9 +60,13 @@ ALG_BYTES_PER_RECORD = 28  # src_ip, dst_ip, bytes, packets, first_ms, last_ms
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E peak
 
 
-def event_stride(windows: int) -> int:
-    """Plain steps between event-bracketed ones: the smallest odd prime not dividing the window count."""
-    return next((c for c in (3, 5, 7, 11, 13) if windows % c), 1)
+EVENT_GROUP = 3  # consecutive plain steps between one pair of HIP events
+
+
+def event_period(windows: int) -> int:
+    """Plain steps from one event-bracketed group to the next: the smallest prime above
+    EVENT_GROUP that does not divide the window count, so the groups visit every window."""
+    return next((c for c in (5, 7, 11, 13) if windows % c), EVENT_GROUP)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_classify_plain_large.txt")
 POOL_STREAMS = 5           # 64-site record pool: 5 x 10 M records
 POOL_STREAM_BASE = 100
@@ -299,19 +303,28 @@ def main():
         plain_step(s % args.windows)
     torch.cuda.synchronize()
     # A HIP event pair costs about 7 us of GPU time per step here (a 10 M window
-    # takes 102.9 us per step without events, 110.1 us with a pair on every
-    # step), so events bracket every stride-th timed step: a stride prime to
-    # the window count, so every window is sampled.
-    stride = event_stride(args.windows)
-    evs = {s: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for s in range(0, args.steps, stride)}
+    # takes 102.9 us per step without events, 110.1 us with a pair around every
+    # step), and part of it falls inside the interval it measures.  So one pair
+    # brackets each group of EVENT_GROUP back-to-back steps, a group starting
+    # every `period` steps, and a call's time is the group's interval divided
+    # by EVENT_GROUP.
+    if args.steps < EVENT_GROUP:
+        raise SystemExit("--steps must be at least %d" % EVENT_GROUP)
+    period = event_period(args.windows)
+    starts = [s for s in range(0, args.steps - EVENT_GROUP + 1, period)]
+    evs = {s: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for s in starts}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        plain_step(s % args.windows, evs.get(s))
+        g = s - (s % period)
+        if g in evs and s == g:
+            evs[g][0].record()
+        plain_step(s % args.windows)
+        if g in evs and s == g + EVENT_GROUP - 1:
+            evs[g][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms = [a.elapsed_time(b) for a, b in evs.values()]
+    kms = [a.elapsed_time(b) / EVENT_GROUP for a, b in evs.values()]
     k_avg = float(np.mean(kms))
     value = args.steps * n_win / wall
     log("plain: %.3f ms/step, classify call avg %.4f ms (min %.4f) -> %.1f GB/s" %
@@ -798,7 +811,8 @@ def main():
             "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
             "kernel": "classify_kernel + reduce_partials_kernel (one classify_flag call)",
             "kernel_ms_avg": k_avg,
-            "kernel_ms_from": "HIP events around every %dth timed step (%d of %d)" % (stride, len(kms), args.steps),
+            "kernel_ms_from": "HIP events around %d groups of %d consecutive timed steps (of %d), one group "
+                              "every %d steps" % (len(kms), EVENT_GROUP, args.steps, period),
         },
         "cpu_baseline": cpu,
         "parity": parity,
