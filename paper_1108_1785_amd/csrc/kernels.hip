@@ -904,20 +904,34 @@ struct FlagArgs {
 // the window.
 __global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
     const u64 *__restrict__ ws, const uint32_t *__restrict__ meta, uint32_t slots, uint32_t rows,
-    u64 *__restrict__ acc, uint32_t row_tiles, uint32_t overwrite, FlagArgs fl) {
+    u64 *__restrict__ acc, uint32_t row_tiles, uint32_t overwrite, uint32_t one_window, FlagArgs fl) {
   const uint32_t w = blockIdx.x / row_tiles, tile = blockIdx.x - w * row_tiles;
-  uint32_t b0 = 0, len = slots;  // first slot with meta >= w
-  while (len > 0) {
-    const uint32_t half = len >> 1;
-    if (meta[b0 + half] < w) { b0 += half + 1; len -= half + 1; }
-    else len = half;
-  }
-  uint32_t b1 = b0;
-  len = slots - b0;  // first slot with meta > w
-  while (len > 0) {
-    const uint32_t half = len >> 1;
-    if (meta[b1 + half] <= w) { b1 += half + 1; len -= half + 1; }
-    else len = half;
+  // window w's slots [b0, b1): the slot windows are sorted, so b0 counts the
+  // slots of earlier windows and b1 adds w's own; every lane counts a strided
+  // share in one round of independent loads.  A single window owns them all.
+  uint32_t b0 = 0, b1 = slots;
+  if (!one_window) {
+    __shared__ uint32_t counts[2];
+    if (threadIdx.x < 2u) counts[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t lt = 0, le = 0;
+    for (uint32_t k = threadIdx.x; k < slots; k += blockDim.x) {
+      const uint32_t m = meta[k];
+      lt += m < w;
+      le += m <= w;
+    }
+#pragma unroll
+    for (uint32_t o = 32; o > 0; o >>= 1) {
+      lt += __shfl_xor(lt, o, 64);
+      le += __shfl_xor(le, o, 64);
+    }
+    if (threadIdx.x % 64u == 0u && le) {
+      atomicAdd(&counts[0], lt);
+      atomicAdd(&counts[1], le);
+    }
+    __syncthreads();
+    b0 = counts[0];
+    b1 = counts[1];
   }
   const bool any = b0 < b1;
   if (!any && !fl.flags) return;
@@ -1425,7 +1439,7 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   if (use_ws) {
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(row_tiles * n_windows)), dim3(64 * kRedGroups), 0,
                        stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta, (uint32_t)grid, (uint32_t)rows,
-                       (u64 *)acc, (uint32_t)row_tiles, overwrite ? 1u : 0u, fl);
+                       (u64 *)acc, (uint32_t)row_tiles, overwrite ? 1u : 0u, n_windows == 1 ? 1u : 0u, fl);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
   } else {
