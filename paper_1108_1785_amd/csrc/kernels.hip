@@ -54,7 +54,7 @@ typedef __attribute__((address_space(1))) const uint64_t gu64;
 constexpr uint32_t kThreads = 1024;
 constexpr uint32_t kRedRows = 8;     // reduce kernel: table rows (4 sites) per workgroup
 constexpr uint32_t kRedWords = kRedRows * kAccFields;  // reduce kernel: 56 table words, one per lane
-constexpr uint32_t kRedGroups = 16;  // reduce kernel: waves, each summing every 16th slot
+constexpr uint32_t kRedGroups = 16;  // reduce kernel: at most 16 waves, each summing every G-th slot
 constexpr uint32_t kRedUnroll = 8;   // reduce kernel: slot loads in flight per lane
 constexpr uint32_t kBuckets = 10001;      // rate histogram: 10 kbps buckets, the last for > 100 Mbps
 constexpr uint32_t kBucketBps = 10000;
@@ -895,8 +895,9 @@ struct FlagArgs {
 // contiguous range (slot windows never decrease).  Workgroup
 // w * row_tiles + x owns rows 8x .. 8x + 7 (sites 4x .. 4x + 3) of window w's
 // table, 56 consecutive words of the flattened table (rows of kAccFields
-// words): lane j < 56 of each of its 16 waves reads word j of every 16th slot,
-// so each wave load is one contiguous 448-byte run, and the waves' partial
+// words): lane j < 56 of each of its G waves (G = blockDim.x / 64, 1..16, set
+// by the host from the slots per window) reads word j of every G-th slot, so
+// each wave load is one contiguous 448-byte run, and the waves' partial
 // results meet in LDS.  Adds into acc, or overwrites it when the classify
 // launch left no other contribution.  With flags, wave 0 then holds the final
 // bulk-flow counts and rate sums of the tile's rows and applies the mean-rate
@@ -935,7 +936,7 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
   }
   const bool any = b0 < b1;
   if (!any && !fl.flags) return;
-  const uint32_t lane = threadIdx.x % 64u, g = threadIdx.x / 64u;
+  const uint32_t lane = threadIdx.x % 64u, g = threadIdx.x / 64u, groups = blockDim.x / 64u;
   const uint32_t words = kAccFields * rows;
   const uint32_t i = tile * kRedWords + lane;
   const bool mine = lane < kRedWords && i < words;
@@ -947,16 +948,16 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
     const u64 *p = ws + i;
     // kRedUnroll loads in flight per lane (indexes past the range reload its
     // last slot and are masked), then branch-free combining
-    for (uint32_t base = b0 + g; base < b1; base += kRedGroups * kRedUnroll) {
+    for (uint32_t base = b0 + g; base < b1; base += groups * kRedUnroll) {
       u64 v[kRedUnroll];
 #pragma unroll
       for (uint32_t j = 0; j < kRedUnroll; ++j) {
-        const uint32_t b = base + j * kRedGroups;
+        const uint32_t b = base + j * groups;
         v[j] = __builtin_nontemporal_load(p + (uint64_t)(b < b1 ? b : b1 - 1u) * words);
       }
 #pragma unroll
       for (uint32_t j = 0; j < kRedUnroll; ++j) {
-        const bool ok = base + j * kRedGroups < b1;
+        const bool ok = base + j * groups < b1;
         const u64 val = v[j];
         xs += ok ? (is_cnt ? (val & 0xFFFFFFFFull) : val) : 0ull;
         y += ok && is_cnt ? val >> 32 : 0ull;
@@ -971,7 +972,7 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
   red[g][1][lane] = y;
   __syncthreads();
   if (g != 0) return;
-  for (uint32_t s = 1; s < kRedGroups; ++s) {
+  for (uint32_t s = 1; s < groups; ++s) {
     const u64 v = red[s][0][lane];
     if (f == kRateMin) x = v < x ? v : x;
     else if (f == kRateMax) x = v > x ? v : x;
@@ -1437,7 +1438,12 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
   if (use_ws) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(row_tiles * n_windows)), dim3(64 * kRedGroups), 0,
+    // waves per reduce workgroup: the mean slots per window, rounded up to a
+    // power of two, at most kRedGroups
+    const uint64_t per_window = (grid + n_windows - 1) / n_windows;
+    uint32_t groups = 1;
+    while (groups < kRedGroups && groups < per_window) groups *= 2;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(row_tiles * n_windows)), dim3(64 * groups), 0,
                        stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta, (uint32_t)grid, (uint32_t)rows,
                        (u64 *)acc, (uint32_t)row_tiles, overwrite ? 1u : 0u, n_windows == 1 ? 1u : 0u, fl);
     e = hipGetLastError();
