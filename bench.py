@@ -223,8 +223,8 @@ def main():
                     help="run one device copy of this many MiB first (scale for FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this path has no multi-GPU launch (records shard with no "
-              "exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: windows would shard across GPUs with no exchange, and this "
+              "path has no multi-GPU launch. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import flowgen

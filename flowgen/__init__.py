@@ -9,9 +9,8 @@ computation.
 
 The workloads stand in for the paper's measurement data, which is not
 available: real border-router NetFlow v5 records (§IV.A: 50 million records,
-100 registered /24 subnets).  Distributions follow the recipe written down in
-the design notes: heavy-tailed (lognormal) byte counts, uniform durations up
-to five minutes, Zipf-distributed site popularity, 90 % of records with one
+100 registered /24 subnets).  Distributions follow one fixed recipe:
+heavy-tailed (lognormal) byte counts, uniform durations up to five minutes, Zipf-distributed site popularity, 90 % of records with one
 local endpoint and 10 % of remote endpoints outside every registered site.
 
 All arrays are little-endian numpy arrays.  IPv4 addresses are host-order

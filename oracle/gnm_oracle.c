@@ -23,8 +23,8 @@
  * Readings where the paper is silent (longest-prefix match over /0../32, the
  * direction from the local endpoint, the NODIR and unmatched rows, the integer
  * rate floor(bytes*8000/duration_ms) with decimal units, bulk eligibility
- * bytes > threshold and duration > 0) are listed in the design notes; each
- * function below names the one it implements.
+ * bytes > threshold and duration > 0) are fixed readings; each function
+ * below names the one it implements.
  */
 #include <stdint.h>
 #include <stdlib.h>
