@@ -916,10 +916,18 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
     if (threadIdx.x < 2u) counts[threadIdx.x] = 0u;
     __syncthreads();
     uint32_t lt = 0, le = 0;
-    for (uint32_t k = threadIdx.x; k < slots; k += blockDim.x) {
-      const uint32_t m = meta[k];
-      lt += m < w;
-      le += m <= w;
+    for (uint32_t k0 = threadIdx.x; k0 < slots; k0 += 8u * blockDim.x) {
+      uint32_t m[8];  // eight loads in flight; past the end, a tag above every window
+#pragma unroll
+      for (uint32_t j = 0; j < 8u; ++j) {
+        const uint32_t k = k0 + j * blockDim.x;
+        m[j] = k < slots ? meta[k] : ~0u;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < 8u; ++j) {
+        lt += m[j] < w;
+        le += m[j] <= w;
+      }
     }
 #pragma unroll
     for (uint32_t o = 32; o > 0; o >>= 1) {
@@ -967,17 +975,19 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
     }
   }
   u64 x = is_min ? xmin : (is_max ? xmax : xs);
-  __shared__ u64 red[kRedGroups][2][64];
-  red[g][0][lane] = x;
-  red[g][1][lane] = y;
+  // the waves' partial results: 1 KB of dynamic LDS per wave (a small
+  // workgroup takes little LDS, so many fit a CU at once)
+  extern __shared__ u64 red[];  // [groups][2][64]
+  red[(2u * g) * 64u + lane] = x;
+  red[(2u * g + 1u) * 64u + lane] = y;
   __syncthreads();
   if (g != 0) return;
   for (uint32_t s = 1; s < groups; ++s) {
-    const u64 v = red[s][0][lane];
+    const u64 v = red[(2u * s) * 64u + lane];
     if (f == kRateMin) x = v < x ? v : x;
     else if (f == kRateMax) x = v > x ? v : x;
     else x += v;
-    y += red[s][1][lane];
+    y += red[(2u * s + 1u) * 64u + lane];
   }
   // table word (row, f) -> acc fields: cnt -> flows (0) and bulk flows (4);
   // bytes, packets, duration -> 1..3; rate sum, min, max -> 5..7.  fx, fy:
@@ -1438,12 +1448,14 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
   if (use_ws) {
-    // waves per reduce workgroup: the mean slots per window, rounded up to a
-    // power of two, at most kRedGroups
-    const uint64_t per_window = (grid + n_windows - 1) / n_windows;
+    // waves per reduce workgroup: enough for one round of kRedUnroll loads per
+    // lane over the mean slots per window, rounded up to a power of two, at
+    // most kRedGroups (smaller workgroups fit more per CU at once)
+    const uint64_t rounds = ((grid + n_windows - 1) / n_windows + kRedUnroll - 1) / kRedUnroll;
     uint32_t groups = 1;
-    while (groups < kRedGroups && groups < per_window) groups *= 2;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(row_tiles * n_windows)), dim3(64 * groups), 0,
+    while (groups < kRedGroups && groups < rounds) groups *= 2;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((uint32_t)(row_tiles * n_windows)), dim3(64 * groups),
+                       groups * 2u * 64u * sizeof(u64),
                        stream, (const u64 *)a.ws, (const uint32_t *)a.ws_meta, (uint32_t)grid, (uint32_t)rows,
                        (u64 *)acc, (uint32_t)row_tiles, overwrite ? 1u : 0u, n_windows == 1 ? 1u : 0u, fl);
     e = hipGetLastError();
