@@ -195,3 +195,32 @@ def test_fused_flag_plain_large_1m(torch_cuda):
         _, got, fl = fused(reg, rec, None, thr, 0, True)
         assert (got[0] == exp).all(), diff(got[0], exp)
         assert (fl[0] == oracle.flags(exp, r.n_sites, thr)).all()
+
+
+def test_fused_flag_with_histograms_hosts_and_filters(torch_cuda):
+    # every option of the classify call at once, with the flag test fused
+    import torch
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec, n_sites = s["rec"], s["reg"].n_sites
+    f = {"min_avg_packet_bytes": 100, "min_packets": 1000, "min_duration_ms": 5000}
+    exp = s["orc"].classify_aggregate(rec, filters=f)
+    thr = mean_rates(exp, n_sites)[len(mean_rates(exp, n_sites)) // 2]
+    for ws in (True, False):
+        say("case: fused flag with histograms, hosts and filters, workspace", ws)
+        acc = torch.empty((1, reg.rows, 8), dtype=torch.int64, device=DEV)
+        flags = torch.full((n_sites,), 0xA5, dtype=torch.uint8, device=DEV)
+        hist = gnm.make_rate_hist(reg, 1)
+        hosts = gnm.HostTable(1 << 16, device=DEV)
+        gnm.classify_flag(reg, to_device(rec), acc, flags, thr, 0, n=rec.n, rate_hist=hist, hosts=hosts, filters=f,
+                          workspace=gnm.make_workspace(reg) if ws else None)
+        torch.cuda.synchronize()
+        got = gnm.acc_to_numpy(acc)[0]
+        assert (got == exp).all(), diff(got, exp)
+        assert (flags.cpu().numpy() == oracle.flags(exp, n_sites, thr)).all()
+        S2 = 2 * n_sites
+        h = hist.cpu().numpy().view(np.uint32).reshape(1, S2, -1)
+        assert (h == oracle.rate_histograms(s["orc"], rec, filters=f)[:, :S2]).all()
+        keys, st, used, dropped = hosts.to_numpy()
+        ek, es = oracle.host_stats(s["orc"], rec, filters=f)
+        assert dropped == 0 and used == keys.size and (keys == ek).all() and (st == es).all()

@@ -407,6 +407,7 @@ def test_graph_replays_match_oracle(torch_cuda):
         for f in d:
             d[f].copy_(src[f])  # refill the captured buffers (eager work between replays)
         acc.fill_(7)
+        flg.fill_(0xA5)  # every replay must write every flag
         torch.cuda.synchronize()
         g.launch()
         torch.cuda.synchronize()
