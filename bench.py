@@ -60,13 +60,13 @@ ALG_BYTES_PER_RECORD = 28  # src_ip, dst_ip, bytes, packets, first_ms, last_ms
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E peak
 
 
-EVENT_GROUP = 3  # consecutive plain steps between one pair of HIP events
+EVENT_GROUP = 5  # consecutive plain steps between one pair of HIP events
 
 
 def event_period(windows: int) -> int:
     """Plain steps from one event-bracketed group to the next: the smallest prime above
     EVENT_GROUP that does not divide the window count, so the groups visit every window."""
-    return next((c for c in (5, 7, 11, 13) if windows % c), EVENT_GROUP)
+    return next((c for c in (7, 11, 13, 17) if windows % c), EVENT_GROUP)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_classify_plain_large.txt")
 POOL_STREAMS = 5           # 64-site record pool: 5 x 10 M records
 POOL_STREAM_BASE = 100
@@ -305,13 +305,14 @@ def main():
     # A HIP event pair costs about 7 us of GPU time per step here (a 10 M window
     # takes 102.9 us per step without events, 110.1 us with a pair around every
     # step), and part of it falls inside the interval it measures.  So one pair
-    # brackets each group of EVENT_GROUP back-to-back steps, a group starting
-    # every `period` steps, and a call's time is the group's interval divided
-    # by EVENT_GROUP.
-    if args.steps < EVENT_GROUP:
-        raise SystemExit("--steps must be at least %d" % EVENT_GROUP)
-    period = event_period(args.windows)
-    starts = [s for s in range(0, args.steps - EVENT_GROUP + 1, period)]
+    # brackets each group of `group` back-to-back steps (EVENT_GROUP, or all
+    # of a shorter run), a group starting every `period` steps, and a call's
+    # time is the group's interval divided by `group`.
+    if args.steps < 1:
+        raise SystemExit("--steps must be at least 1")
+    group = min(EVENT_GROUP, args.steps)
+    period = max(event_period(args.windows), group)
+    starts = [s for s in range(0, args.steps - group + 1, period)]
     evs = {s: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for s in starts}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -320,11 +321,11 @@ def main():
         if g in evs and s == g:
             evs[g][0].record()
         plain_step(s % args.windows)
-        if g in evs and s == g + EVENT_GROUP - 1:
+        if g in evs and s == g + group - 1:
             evs[g][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms = [a.elapsed_time(b) / EVENT_GROUP for a, b in evs.values()]
+    kms = [a.elapsed_time(b) / group for a, b in evs.values()]
     k_avg = float(np.mean(kms))
     value = args.steps * n_win / wall
     log("plain: %.3f ms/step, classify call avg %.4f ms (min %.4f) -> %.1f GB/s" %
@@ -812,7 +813,7 @@ def main():
             "kernel": "classify_kernel + reduce_partials_kernel (one classify_flag call)",
             "kernel_ms_avg": k_avg,
             "kernel_ms_from": "HIP events around %d groups of %d consecutive timed steps (of %d), one group "
-                              "every %d steps" % (len(kms), EVENT_GROUP, args.steps, period),
+                              "every %d steps" % (len(kms), group, args.steps, period),
         },
         "cpu_baseline": cpu,
         "parity": parity,
