@@ -909,7 +909,7 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_partials_kernel(
   const uint32_t w = blockIdx.x / row_tiles, tile = blockIdx.x - w * row_tiles;
   // window w's slots [b0, b1): the slot windows are sorted, so b0 counts the
   // slots of earlier windows and b1 adds w's own; every lane counts a strided
-  // share in one round of independent loads.  A single window owns them all.
+  // share, eight independent loads at a time.  A single window owns them all.
   uint32_t b0 = 0, b1 = slots;
   if (!one_window) {
     __shared__ uint32_t counts[2];
