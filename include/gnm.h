@@ -150,7 +150,11 @@ typedef struct {
   uint32_t flags;              /* GNM_ACCUMULATE */
   uint32_t records_per_thread; /* 0 = automatic (4); else 1, 2 or 4 */
   uint32_t grid_blocks;        /* 0 = automatic; else workgroups of the launch */
-  uint32_t reserved;
+  uint32_t flush_records;      /* records a workgroup aggregates in LDS before it flushes its table to the
+                                  window table (device-scope atomics) and starts again: 0 = 2^31, the
+                                  maximum (larger values are clamped to it, since a table row counts
+                                  flows and bulk flows in 32 bits each).  Only tests lower it, to
+                                  exercise the mid-launch flush; results do not depend on it */
   void *workspace;             /* optional DEVICE scratch, 16-byte aligned; see below */
   uint64_t workspace_bytes;    /* its size; >= gnm_workspace_bytes(reg, grid_blocks) to be used */
   uint32_t *rate_hist;         /* optional DEVICE rate histograms (layout above), 16-byte aligned: NULL = none;
@@ -392,9 +396,10 @@ typedef struct gnm_graph gnm_graph; /* opaque */
  * threshold_bps, min_bulk_flows, flags).  All pointers (records, offsets, acc, flags, p->workspace,
  * p->rate_hist) are
  * baked into the graph: every replay reads and writes those same buffers,
- * whose contents the caller may change between replays.  The call runs the
- * step once eagerly (results valid on return) and synchronises its own
- * private stream.  Errors: those of the two captured calls, GNM_E_HIP.
+ * whose contents the caller may change between replays.  The call validates
+ * the arguments and sets up the kernels without running the step (so a step
+ * with GNM_ACCUMULATE adds once per replay, and only then); the first replay
+ * computes the results.  Errors: those of the two captured calls, GNM_E_HIP.
  */
 int gnm_graph_create(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
                      uint32_t n_windows, const gnm_params *p, gnm_acc *acc, uint64_t threshold_bps,
@@ -424,9 +429,12 @@ typedef struct {
  * and quadruple workgroup counts), each as a warm-up plus the median of `reps`
  * (0 = 3) timed calls on `stream`, and return the fastest.  acc is
  * overwritten (initialised per call unless base->flags has GNM_ACCUMULATE,
- * in which case it accumulates every timed call).  Candidates whose
- * workgroup count needs more workspace than base->workspace_bytes merge with
- * atomics.  Synchronous.  Errors: those of gnm_classify_aggregate, GNM_E_HIP.
+ * in which case it accumulates every timed call).  Without a workspace
+ * every candidate merges with atomics; with base->workspace set, candidates
+ * whose workgroup count needs more workspace than base->workspace_bytes are
+ * skipped, so every shape timed merges the way the tuned launch with that
+ * workspace will.
+ * Synchronous.  Errors: those of gnm_classify_aggregate, GNM_E_HIP.
  */
 int gnm_autotune(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
                  uint32_t n_windows, const gnm_params *base, gnm_acc *acc, uint32_t reps,

@@ -67,7 +67,7 @@ class RecordsOutC(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("bulk_bytes", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("records_per_thread", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
+                ("flush_records", ctypes.c_uint32), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_uint64), ("rate_hist", ctypes.c_void_p),
                 ("min_avg_packet_bytes", ctypes.c_uint32), ("min_packets", ctypes.c_uint32),
                 ("min_duration_ms", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
@@ -316,14 +316,19 @@ def records_struct(rec: Dict[str, "object"], n: Optional[int] = None) -> Records
 
 
 def make_params(bulk_bytes: int = 1_000_000, accumulate: bool = False, records_per_thread: int = 0,
-                grid_blocks: int = 0, workspace=None, rate_hist=None, filters=None, hosts=None) -> Params:
+                grid_blocks: int = 0, workspace=None, rate_hist=None, filters=None, hosts=None,
+                flush_records: int = 0) -> Params:
     """filters: optional dict of exclusion thresholds (FILTER_KEYS), 0 = off.
-    hosts: optional HostTable (the caller keeps it alive while work is queued)."""
+    hosts: optional HostTable (the caller keeps it alive while work is queued).
+    flush_records: records a workgroup aggregates between table flushes (0 = 2^31)."""
     p = lib().gnm_params_default()
     p.bulk_bytes = int(bulk_bytes)
     p.flags = GNM_ACCUMULATE if accumulate else 0
     p.records_per_thread = int(records_per_thread)
     p.grid_blocks = int(grid_blocks)
+    if not 0 <= int(flush_records) < 2**32:
+        raise ValueError("flush_records must fit 32 bits")
+    p.flush_records = int(flush_records)
     if workspace is not None:
         if not workspace.is_cuda or not workspace.is_contiguous():
             raise ValueError("workspace must be a contiguous device tensor")
@@ -376,7 +381,7 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
                        bulk_bytes: int = 1_000_000, accumulate: bool = False,
                        records_per_thread: int = 0, grid_blocks: int = 0, stream=None,
                        n: Optional[int] = None, workspace=None, rate_hist=None, filters=None,
-                       hosts=None) -> None:
+                       hosts=None, flush_records: int = 0) -> None:
     """gnm_classify_aggregate: acc is a device tensor of n_windows*rows*8 64-bit words.
 
     workspace: optional device tensor from make_workspace() (faster table merge).
@@ -385,14 +390,14 @@ def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: 
     hosts: optional HostTable for per-host statistics.
     """
     c, off, p = _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumulate, records_per_thread,
-                               grid_blocks, n, workspace, rate_hist, filters, hosts)
+                               grid_blocks, n, workspace, rate_hist, filters, hosts, flush_records)
     _check(lib().gnm_classify_aggregate(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
                                         ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()),
                                         _stream_handle(stream)), "gnm_classify_aggregate")
 
 
 def _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumulate, records_per_thread,
-                   grid_blocks, n, workspace, rate_hist, filters, hosts):
+                   grid_blocks, n, workspace, rate_hist, filters, hosts, flush_records=0):
     c = rec if isinstance(rec, RecordsC) else records_struct(rec, n)
     if acc.element_size() * acc.numel() < n_windows * reg.rows * 64 or not acc.is_cuda:
         raise ValueError("acc must be a device tensor of n_windows * rows * 64 bytes")
@@ -403,21 +408,22 @@ def _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumul
         off = window_offsets.data_ptr()
     if rate_hist is not None and rate_hist.numel() < rate_hist_words(reg, n_windows):
         raise ValueError("rate_hist must hold n_windows * 2 * n_sites * 10001 counts")
-    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist, filters, hosts)
+    p = make_params(bulk_bytes, accumulate, records_per_thread, grid_blocks, workspace, rate_hist, filters, hosts,
+                    flush_records)
     return c, off, p
 
 
 def classify_flag(reg: Registry, rec, acc, flags, threshold_bps: int = 1_000_000, min_bulk_flows: int = 0,
                   window_offsets=None, n_windows: int = 1, bulk_bytes: int = 1_000_000, accumulate: bool = False,
                   records_per_thread: int = 0, grid_blocks: int = 0, stream=None, n: Optional[int] = None,
-                  workspace=None, rate_hist=None, filters=None, hosts=None) -> None:
+                  workspace=None, rate_hist=None, filters=None, hosts=None, flush_records: int = 0) -> None:
     """gnm_classify_flag: classify_aggregate then flag_suboptimal in one call (the flag
     test fused into the table merge when a workspace is given); same arguments as
     those two."""
     if flags.element_size() != 1 or flags.numel() < n_windows * reg.n_sites or not flags.is_cuda:
         raise ValueError("flags must be a device uint8 tensor of n_windows * n_sites bytes")
     c, off, p = _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumulate, records_per_thread,
-                               grid_blocks, n, workspace, rate_hist, filters, hosts)
+                               grid_blocks, n, workspace, rate_hist, filters, hosts, flush_records)
     _check(lib().gnm_classify_flag(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
                                    ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()), int(threshold_bps),
                                    int(min_bulk_flows), ctypes.c_void_p(flags.data_ptr()),

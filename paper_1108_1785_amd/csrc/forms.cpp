@@ -40,18 +40,14 @@ extern "C" int gnm_graph_create(const gnm_registry *reg, const gnm_records *rec,
   *out = nullptr;
   if (!reg || !rec || !acc) { set_last_error("NULL argument"); return GNM_E_INVAL; }
   if (reg->host_only) { set_last_error("registry was built host-only"); return GNM_E_UNSUPPORTED; }
-  // One eager call validates the arguments and performs every one-time
-  // set-up (kernel attributes) outside the capture.
+  // Every argument is validated and every one-time set-up (kernel attributes)
+  // is done outside the capture, without running the step: a run here would
+  // add into acc a second time when the step accumulates.
+  int rc = classify_prepare(reg, rec, window_offsets, n_windows, p, acc, flags);
+  if (rc != GNM_OK) return rc;
   hipStream_t s = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_err(e, "hipStreamCreate");
-  int rc = flags ? gnm_classify_flag(reg, rec, window_offsets, n_windows, p, acc, threshold_bps, min_bulk_flows,
-                                     flags, s)
-                : gnm_classify_aggregate(reg, rec, window_offsets, n_windows, p, acc, s);
-  if (rc == GNM_OK) {
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) rc = hip_err(e, "hipStreamSynchronize");
-  }
   gnm_graph *g = nullptr;
   if (rc == GNM_OK) {
     g = new (std::nothrow) gnm_graph();
@@ -132,6 +128,9 @@ extern "C" int gnm_autotune(const gnm_registry *reg, const gnm_records *rec, con
   for (uint32_t rpt : rpts) {
     for (uint32_t grid : grids) {
       if (n >= GNM_TUNE_MAX) break;
+      // with a workspace, only shapes whose partial tables fit it: every
+      // candidate then merges the same way as the tuned launch will
+      if (b.workspace && reg->acc_in_lds && gnm_workspace_bytes(reg, grid) > b.workspace_bytes) continue;
       gnm_params p = b;
       p.records_per_thread = rpt;
       p.grid_blocks = grid;

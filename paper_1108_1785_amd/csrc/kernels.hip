@@ -84,6 +84,7 @@ struct ClassifyArgs {
   const uint64_t *bytes;
   const uint32_t *packets, *first, *last;
   uint64_t n;
+  uint64_t flush_records;  // records aggregated in LDS between two table flushes (<= kMaxRecordsPerFlush)
   gu64 *woff;  // NULL: one window [0, n)
   uint32_t n_windows;
   uint32_t rows;
@@ -852,7 +853,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     uint64_t wend;
     const uint32_t w = window_of(a, i, wend);
     uint64_t seg_end = wend < hi ? wend : hi;
-    if (seg_end - i > kMaxRecordsPerFlush) seg_end = i + kMaxRecordsPerFlush;
+    if (seg_end - i > a.flush_records) seg_end = i + a.flush_records;
     u64 *g_tab = a.acc + (uint64_t)w * rows * 8u;
     uint32_t *h_tab = HIST ? a.hist + (uint64_t)w * a.hist_rows * kBuckets : nullptr;
 
@@ -1291,10 +1292,13 @@ namespace {
 
 // gnm_classify_aggregate, and with fl.flags also gnm_flag_suboptimal on the
 // result: fused into the reduce kernel when the workspace is used, otherwise
-// the flag kernel after the classify launch.
+// the flag kernel after the classify launch.  Every argument is validated and
+// the kernel attributes are set before anything is enqueued; with
+// launch == false the call stops there (a graph's validation, outside
+// capture).
 int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
                   uint32_t n_windows, const gnm_params *pp, gnm_acc *acc, const FlagArgs &fl,
-                  hipStream_t stream) {
+                  hipStream_t stream, bool launch) {
   if (!reg || !rec || !acc) { set_last_error("NULL argument"); return GNM_E_INVAL; }
   if (reg->host_only) { set_last_error("registry was built host-only"); return GNM_E_UNSUPPORTED; }
   if (n_windows == 0) { set_last_error("n_windows must be >= 1"); return GNM_E_INVAL; }
@@ -1305,6 +1309,8 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     return GNM_E_INVAL;
   }
   const gnm_params p = pp ? *pp : gnm_params_default();
+  const uint64_t flush_records =
+      p.flush_records && p.flush_records < kMaxRecordsPerFlush ? p.flush_records : kMaxRecordsPerFlush;
   const uint32_t R = p.records_per_thread ? p.records_per_thread : 4u;
   if (R != 1 && R != 2 && R != 4) { set_last_error("records_per_thread must be 0, 1, 2 or 4"); return GNM_E_INVAL; }
   int dev = -1;
@@ -1342,7 +1348,62 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   // need no mid-launch flush, the reduce kernel writes every row of the
   // table, so it needs no initialisation.
   const bool overwrite = use_ws && n_windows == 1 && !(p.flags & GNM_ACCUMULATE) &&
-                         (rec->n + grid - 1) / grid <= kMaxRecordsPerFlush;
+                         (rec->n + grid - 1) / grid <= flush_records;
+
+  ClassifyArgs a{};
+  a.src = rec->src_ip; a.dst = rec->dst_ip; a.bytes = rec->bytes; a.packets = rec->packets;
+  a.first = rec->first_ms; a.last = rec->last_ms; a.n = rec->n;
+  a.flush_records = flush_records;
+  a.woff = (gu64 *)window_offsets; a.n_windows = n_windows; a.rows = (uint32_t)rows;
+  a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
+  a.min_avg_packet_bytes = p.min_avg_packet_bytes; a.min_packets = p.min_packets;
+  a.min_duration_ms = p.min_duration_ms;
+  a.filters = (p.min_avg_packet_bytes | p.min_packets | p.min_duration_ms) != 0u;
+  a.root = (gu64 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
+  a.root_bits = reg->root_bits; a.node_bits = reg->node_bits; a.n_line_words = (uint32_t)reg->lines.size();
+  a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
+  a.cache_slots = reg->acc_in_lds ? 0u : reg->cache_slots;
+  a.hist = p.rate_hist;
+  a.hist_rows = 2u * reg->n_sites;
+  if (ht) {
+    a.host_keys = (u64 *)ht->keys;
+    a.host_stats = (u64 *)ht->stats;
+    a.host_mask = ht->capacity - 1u;
+    a.host_counters = (u64 *)ht->counters;
+  }
+  uint32_t lds_launch = reg->lds_bytes;
+  if (p.rate_hist) {
+    // the histogram cache takes the LDS the registry leaves free, within the
+    // budget that keeps the registry's workgroups per CU
+    const uint32_t off = (reg->lds_bytes + 15u) & ~15u;
+    const uint32_t budget = reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax;
+    uint32_t hs = budget > off ? (budget - off) / 8u : 0u;
+    hs = (hs < kHistSlotsMax ? hs : kHistSlotsMax) & ~3u;
+    if (hs < 64u) hs = 0;
+    a.lds_off_hist = off;
+    a.hist_slots = hs;
+    lds_launch = off + hs * 8u;
+  }
+  if (use_ws) {
+    a.ws = (u64 *)p.workspace;
+    a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);
+  }
+  a.local.n = (uint32_t)reg->local_lo.size();
+  for (uint32_t j = 0; j < a.local.n; ++j) {
+    a.local.lo[j] = reg->local_lo[j];
+    a.local.span[j] = reg->local_hi[j] - reg->local_lo[j];
+  }
+
+  const bool vec = R == 4 && aligned16(rec->src_ip) && aligned16(rec->dst_ip) && aligned16(rec->bytes) &&
+                   aligned16(rec->packets) && aligned16(rec->first_ms) && aligned16(rec->last_ms);
+  const int shape = vec ? 3 : (R == 1 ? 0 : (R == 2 ? 1 : 2));
+  const uint32_t feat = (p.rate_hist ? kFeatHist : 0u) | (p.hosts ? kFeatHosts : 0u);
+  KernelFn fn = pick(shape, reg->lines_in_lds, reg->acc_in_lds, feat);
+  if (rec->n > 0) {
+    e = allow_lds(fn, (int)feat * 16 + shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0), dev);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+  }
+  if (!launch) return GNM_OK;
 
   if (!(p.flags & GNM_ACCUMULATE) && !overwrite) {
     const uint64_t words = (uint64_t)n_windows * rows * 8u;
@@ -1394,56 +1455,6 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     return rc == GNM_OK ? count_hosts() : rc;
   }
 
-  ClassifyArgs a{};
-  a.src = rec->src_ip; a.dst = rec->dst_ip; a.bytes = rec->bytes; a.packets = rec->packets;
-  a.first = rec->first_ms; a.last = rec->last_ms; a.n = rec->n;
-  a.woff = (gu64 *)window_offsets; a.n_windows = n_windows; a.rows = (uint32_t)rows;
-  a.bulk_bytes = p.bulk_bytes; a.acc = (u64 *)acc;
-  a.min_avg_packet_bytes = p.min_avg_packet_bytes; a.min_packets = p.min_packets;
-  a.min_duration_ms = p.min_duration_ms;
-  a.filters = (p.min_avg_packet_bytes | p.min_packets | p.min_duration_ms) != 0u;
-  a.root = (gu64 *)reg->d_root; a.wide = (gu32 *)reg->d_wide; a.lines = (gu32 *)reg->d_lines;
-  a.root_bits = reg->root_bits; a.node_bits = reg->node_bits; a.n_line_words = (uint32_t)reg->lines.size();
-  a.lds_off_acc = reg->lds_off_acc; a.lds_off_lines = reg->lds_off_lines;
-  a.cache_slots = reg->acc_in_lds ? 0u : reg->cache_slots;
-  a.hist = p.rate_hist;
-  a.hist_rows = 2u * reg->n_sites;
-  if (ht) {
-    a.host_keys = (u64 *)ht->keys;
-    a.host_stats = (u64 *)ht->stats;
-    a.host_mask = ht->capacity - 1u;
-    a.host_counters = (u64 *)ht->counters;
-  }
-  uint32_t lds_launch = reg->lds_bytes;
-  if (p.rate_hist) {
-    // the histogram cache takes the LDS the registry leaves free, within the
-    // budget that keeps the registry's workgroups per CU
-    const uint32_t off = (reg->lds_bytes + 15u) & ~15u;
-    const uint32_t budget = reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax;
-    uint32_t hs = budget > off ? (budget - off) / 8u : 0u;
-    hs = (hs < kHistSlotsMax ? hs : kHistSlotsMax) & ~3u;
-    if (hs < 64u) hs = 0;
-    a.lds_off_hist = off;
-    a.hist_slots = hs;
-    lds_launch = off + hs * 8u;
-  }
-  if (use_ws) {
-    a.ws = (u64 *)p.workspace;
-    a.ws_meta = (uint32_t *)((char *)p.workspace + grid * kAccFields * rows * 8u);
-  }
-  a.local.n = (uint32_t)reg->local_lo.size();
-  for (uint32_t j = 0; j < a.local.n; ++j) {
-    a.local.lo[j] = reg->local_lo[j];
-    a.local.span[j] = reg->local_hi[j] - reg->local_lo[j];
-  }
-
-  const bool vec = R == 4 && aligned16(rec->src_ip) && aligned16(rec->dst_ip) && aligned16(rec->bytes) &&
-                   aligned16(rec->packets) && aligned16(rec->first_ms) && aligned16(rec->last_ms);
-  const int shape = vec ? 3 : (R == 1 ? 0 : (R == 2 ? 1 : 2));
-  const uint32_t feat = (p.rate_hist ? kFeatHist : 0u) | (p.hosts ? kFeatHosts : 0u);
-  KernelFn fn = pick(shape, reg->lines_in_lds, reg->acc_in_lds, feat);
-  e = allow_lds(fn, (int)feat * 16 + shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0), dev);
-  if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), lds_launch, stream, a);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
@@ -1469,10 +1480,22 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
 
 }  // namespace
 
+namespace gnm {
+// Validation and kernel set-up of a classify step without enqueueing it
+// (gnm_graph_create runs this outside capture, then captures the step).
+int classify_prepare(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                     uint32_t n_windows, const gnm_params *p, gnm_acc *acc, uint8_t *flags) {
+  if (flags && !reg) { set_last_error("NULL argument"); return GNM_E_INVAL; }
+  FlagArgs fl{};
+  if (flags) fl = FlagArgs{flags, 0, 1, reg->n_sites};
+  return classify_impl(reg, rec, window_offsets, n_windows, p, acc, fl, nullptr, false);
+}
+}  // namespace gnm
+
 extern "C" int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
                                       const uint64_t *window_offsets, uint32_t n_windows,
                                       const gnm_params *pp, gnm_acc *acc, hipStream_t stream) {
-  return classify_impl(reg, rec, window_offsets, n_windows, pp, acc, FlagArgs{}, stream);
+  return classify_impl(reg, rec, window_offsets, n_windows, pp, acc, FlagArgs{}, stream, true);
 }
 
 extern "C" int gnm_classify_flag(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
@@ -1481,7 +1504,7 @@ extern "C" int gnm_classify_flag(const gnm_registry *reg, const gnm_records *rec
   if (!flags) { set_last_error("NULL argument"); return GNM_E_INVAL; }
   if (!reg) { set_last_error("NULL argument"); return GNM_E_INVAL; }
   const FlagArgs fl{flags, threshold_bps, min_bulk_flows > 1 ? min_bulk_flows : 1, reg->n_sites};
-  return classify_impl(reg, rec, window_offsets, n_windows, p, acc, fl, stream);
+  return classify_impl(reg, rec, window_offsets, n_windows, p, acc, fl, stream, true);
 }
 
 extern "C" int gnm_flag_suboptimal(const gnm_registry *reg, const gnm_acc *acc, uint32_t n_windows,

@@ -43,4 +43,6 @@ struct gnm_registry {
 
 namespace gnm {
 void set_last_error(const std::string &s);
+int classify_prepare(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                     uint32_t n_windows, const gnm_params *p, gnm_acc *acc, uint8_t *flags);
 }

@@ -88,13 +88,14 @@ class RingArena:
 
 
 class Request:
-    __slots__ = ("rid", "records", "n", "t_arrival", "future", "offset", "copy_event", "t_done")
+    __slots__ = ("rid", "records", "n", "t_arrival", "future", "offset", "copy_event", "ready", "t_done")
 
-    def __init__(self, rid: int, records, n: int, t_arrival: float):
+    def __init__(self, rid: int, records, n: int, t_arrival: float, ready=None):
         self.rid, self.records, self.n, self.t_arrival = rid, records, n, t_arrival
         self.future: Future = Future()
         self.offset = -1
         self.copy_event = None
+        self.ready = ready  # device event after which the records may be read (None: at once)
         self.t_done = 0.0
 
 
@@ -162,11 +163,29 @@ class GpuExecutor:
         """Called once on the scheduler thread before it issues device work."""
         self.torch.cuda.set_device(self.torch.device(self.dev))
 
+    def producer_event(self, records):
+        """Called by submit() on the caller's thread.  Records already in device
+        memory may still be being written by work the caller queued on its
+        current stream (a decode kernel, a copy): an event recorded there now
+        orders the staging copy after that work.  None for host records."""
+        torch = self.torch
+        if not any(getattr(records.get(f), "is_cuda", False) for f in RECORD_FIELDS):
+            return None
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(torch.device(self.dev)))
+        return ev
+
+    def _wait_ready(self, reqs: List[Request]) -> None:
+        for r in reqs:
+            if r.ready is not None:
+                self.copy_stream.wait_event(r.ready)
+
     def start_copy(self, req: Request):
         """Asynchronous host->device copy of the request's records into the arena."""
         torch = self.torch
         if req.n == 0:
             return None
+        self._wait_ready([req])
         with torch.cuda.stream(self.copy_stream):
             for f in RECORD_FIELDS:
                 self.buf[f][req.offset:req.offset + req.n].copy_(req.records[f], non_blocking=True)
@@ -188,6 +207,7 @@ class GpuExecutor:
                 r.copy_event = self.start_copy(r)
             return
         lo, hi = live[0].offset, live[-1].offset + live[-1].n
+        self._wait_ready(live)
         with torch.cuda.stream(self.copy_stream):
             for f in RECORD_FIELDS:
                 torch.cat([r.records[f][:r.n] for r in live], out=self.buf[f][lo:hi])
@@ -283,8 +303,10 @@ class Server:
             f.set_exception(AdmissionError("window of %d records exceeds the arena of %d"
                                            % (n, self.arena.capacity)))
             return f
+        mark = getattr(self.ex, "producer_event", None)
+        ready = mark(records) if mark is not None and n else None
         with self.lock:
-            req = Request(self.next_id, records, n, time.perf_counter() if t_arrival is None else t_arrival)
+            req = Request(self.next_id, records, n, time.perf_counter() if t_arrival is None else t_arrival, ready)
             self.next_id += 1
             self.waiting.append(req)
         self.wake.set()

@@ -27,14 +27,50 @@ def _device_name() -> str:
     return "%s/%s/%d" % (p.name, getattr(p, "gcnArchName", ""), p.multi_processor_count)
 
 
-def workload_key(reg: Registry, n_records: int, n_windows: int) -> str:
+def workload_key(reg: Registry, n_records: int, n_windows: int, workspace_bytes: int = 0) -> str:
     i = reg.info()
     shape = "p%d-s%d-r%d-l%d-li%d-ai%d" % (i["n_prefixes"], i["n_sites"], i["root_bits"], i["list_max"],
                                           i["lines_in_lds"], i["acc_in_lds"])
     # sizes bucketed by powers of two: the best shape changes slowly with size
     nb = int(math.log2(max(n_records, 1)))
     wb = int(math.log2(max(n_windows, 1)))
-    return "%s|%s|%s|n2^%d|w2^%d" % (_device_name(), version(), shape, nb, wb)
+    # the merge path: atomics, or workspace partial tables for shapes up to
+    # the workgroup count the workspace holds (candidates beyond it are not timed)
+    merge = "atomic" if not workspace_bytes or not i["acc_in_lds"] else "ws%d" % max_grid_for(reg, workspace_bytes)
+    return "%s|%s|%s|n2^%d|w2^%d|%s" % (_device_name(), version(), shape, nb, wb, merge)
+
+
+def max_grid_for(reg: Registry, workspace_bytes: int) -> int:
+    """Largest tuning candidate workgroup count whose partial tables fit workspace_bytes (0: none)."""
+    best = 0
+    for g in candidate_grids(reg):
+        if workspace_bytes_for(reg, g) <= workspace_bytes:
+            best = max(best, g)
+    return best
+
+
+def _resident(reg: Registry) -> int:
+    import torch
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    return cus * (2 if reg.info()["lds_bytes"] <= 80 * 1024 else 1)
+
+
+def candidate_grids(reg: Registry):
+    """Workgroup counts gnm_autotune tries (the automatic count is the resident one)."""
+    r = _resident(reg)
+    return [r, r // 2, 2 * r, 4 * r]
+
+
+def workspace_bytes_for(reg: Registry, grid: int) -> int:
+    from . import workspace_bytes
+    return workspace_bytes(reg, grid)
+
+
+def tuning_workspace(reg: Registry, device=None):
+    """A workspace large enough for every tuning candidate, so all of them
+    are timed on the partial-table merge that the tuned launch uses."""
+    from . import make_workspace
+    return make_workspace(reg, max(candidate_grids(reg)), device=device)
 
 
 def _load(path: str) -> Dict[str, dict]:
@@ -63,7 +99,8 @@ def tuned_params(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 
     lib()
     path = cache_path or _cache_path()
     n_rec = int(n if n is not None else rec["src_ip"].numel())
-    key = workload_key(reg, n_rec, n_windows)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    key = workload_key(reg, n_rec, n_windows, ws_bytes)
     data = _load(path)
     if not refresh and key in data:
         hit = dict(data[key])

@@ -21,9 +21,11 @@ def offsets_to_device(off, device=DEV):
 
 
 def run(reg, rec, window_offsets=None, bulk_bytes=1_000_000, acc=None, accumulate=False,
-        records_per_thread=0, grid_blocks=0, dev_rec=None, workspace=None, shift=0):
-    """shift > 0 offsets every field pointer by that many records (misaligned views)."""
-    """Classify/aggregate a host Records run on the GPU; returns uint64 [n_windows?, rows, 8]."""
+        records_per_thread=0, grid_blocks=0, dev_rec=None, workspace=None, shift=0, **params):
+    """Classify/aggregate a host Records run on the GPU; returns uint64 [n_windows?, rows, 8].
+
+    shift > 0 offsets every field pointer by that many records (misaligned
+    views); params go to gnm.classify_aggregate (e.g. flush_records)."""
     import torch
     off = window_offsets if window_offsets is not None else rec.window_offsets
     nw = 1 if off is None else len(off) - 1
@@ -41,7 +43,7 @@ def run(reg, rec, window_offsets=None, bulk_bytes=1_000_000, acc=None, accumulat
     doff = None if off is None else offsets_to_device(off)
     gnm.classify_aggregate(reg, d, acc, window_offsets=doff, n_windows=nw, bulk_bytes=bulk_bytes,
                            accumulate=accumulate, records_per_thread=records_per_thread,
-                           grid_blocks=grid_blocks, n=rec.n, workspace=workspace)
+                           grid_blocks=grid_blocks, n=rec.n, workspace=workspace, **params)
     torch.cuda.synchronize()
     out = gnm.acc_to_numpy(acc)
     return out[0] if off is None else out

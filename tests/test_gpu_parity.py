@@ -418,6 +418,35 @@ def test_graph_replays_match_oracle(torch_cuda):
     g.close()
 
 
+def test_graph_accumulates_once_per_replay(torch_cuda):
+    """A captured step with GNM_ACCUMULATE: creating the graph runs nothing,
+    and each replay adds the records once, so after one plain call and two
+    replays the table is that of the records three times over."""
+    import torch
+    say("case: graph with GNM_ACCUMULATE, one eager call then two replays")
+    s = _small()
+    reg = gnm.Registry.from_generated(s["reg"])
+    rec = s["rec"].slice(0, 70_001)
+    d = to_device(rec)
+    acc = torch.empty((1, reg.rows, 8), dtype=torch.int64, device="cuda:0")
+    ws = gnm.make_workspace(reg)
+    gnm.classify_aggregate(reg, d, acc, n=rec.n, workspace=ws)
+    g = gnm.Graph(reg, d, acc, n=rec.n, workspace=ws, accumulate=True)
+    torch.cuda.synchronize()
+    exp1 = s["orc"].classify_aggregate(rec)
+    got = gnm.acc_to_numpy(acc)[0]
+    assert (got == exp1).all(), diff(got, exp1)
+    g.launch()
+    g.launch()
+    torch.cuda.synchronize()
+    three = flowgen.concat([rec, rec, rec])
+    three.window_offsets = None
+    exp3 = s["orc"].classify_aggregate(three)
+    got = gnm.acc_to_numpy(acc)[0]
+    assert (got == exp3).all(), diff(got, exp3)
+    g.close()
+
+
 def test_autotune_choice_is_exact(torch_cuda, tmp_path):
     import torch
     from paper_1108_1785_amd import tune

@@ -156,3 +156,37 @@ def test_served_device_resident_burst_grouped_staging(small):
         acc, fl = _expect(orc, reg_h.n_sites, w)
         assert (r.acc == acc).all() and (r.flags == fl).all()
     assert stats["admission_waits"] > 0 and stats["launches"] < 60
+
+
+def test_served_waits_for_the_producer_stream(small):
+    """A window written on the caller's stream by queued device work and
+    submitted without a synchronisation: the staging copy waits for that
+    work (an event recorded at submit), so the result is the oracle's, not
+    the buffers' stale contents."""
+    import torch
+
+    from tests._gpu import to_device
+    reg_h, reg, orc, pool = small
+    wins = _windows(pool, [40_000, 25_000, 0, 33_333], 17)
+    src = [to_device(w) for w in wins]
+    # the buffers the caller will submit start as garbage (another window)
+    stale = _windows(pool, [w.n for w in wins], 18)
+    bufs = [to_device(s) for s in stale]
+    torch.cuda.synchronize()
+    srv = _server(reg, capacity=150_000, max_w=8)
+    side = torch.cuda.Stream()  # default priority
+    try:
+        futs = []
+        with torch.cuda.stream(side):
+            for b, s_, w in zip(bufs, src, wins):
+                # a bounded spin, then the real records: both queued, nothing waited on
+                torch.cuda._sleep(20_000_000)
+                for f in b:
+                    b[f].copy_(s_[f], non_blocking=True)
+                futs.append(srv.submit(b, n=w.n))
+        res = [f.result(timeout=60) for f in futs]
+    finally:
+        srv.close()
+    for w, r in zip(wins, res):
+        acc, fl = _expect(orc, reg_h.n_sites, w)
+        assert (r.acc == acc).all() and (r.flags == fl).all()
