@@ -312,6 +312,30 @@ def host_stats(reg: "Registry", rec, bulk_bytes: int = 1_000_000, filters: Optio
     return keys, out
 
 
+def host_medians(reg: "Registry", rec, bulk_bytes: int = 1_000_000, filters: Optional[dict] = None):
+    """Lower-median rate bucket per remote host of a registered site, per
+    direction (§III.B.2, TransRate Kernel: max, min, average and median rates
+    for each host in a registered site, the median read from the host's
+    10 kbps bucket array).
+
+    Keys as in host_stats.  For a host with N bulk flows, its bucket array's
+    cumulative count first reaches ceil(N/2) at the ceil(N/2)-th smallest of
+    its flows' buckets: that bucket is the lower median (the convention of
+    rate_medians).  Returns (uint64 keys sorted ascending, uint32 buckets).
+    """
+    row, is_bulk, rate = _classify_rows(reg, rec, bulk_bytes, filters)
+    sel = is_bulk & (row < 2 * reg.n_sites)
+    remote = np.where(row % 2 == 0, np.asarray(rec.src_ip), np.asarray(rec.dst_ip))[sel]
+    key = (remote.astype(np.uint64) << np.uint64(32)) | row[sel].astype(np.uint64)
+    bucket = rate_bucket(rate[sel])
+    order = np.lexsort((bucket, key))  # by key, then bucket
+    key, bucket = key[order], bucket[order]
+    keys, start = np.unique(key, return_index=True)
+    n = np.diff(np.append(start, key.size))
+    med = bucket[start + (n + 1) // 2 - 1] if keys.size else np.zeros(0, dtype=np.uint32)
+    return keys, med.astype(np.uint32)
+
+
 def median_flags(med: np.ndarray, cnt: np.ndarray, n_sites: int, threshold_bps: int = 1_000_000,
                  min_bulk_flows: int = 0, prev: Optional[np.ndarray] = None) -> np.ndarray:
     """Median warnings per (window, site), one site and window at a time.

@@ -554,3 +554,86 @@ def test_median_worked_example():
     assert cnt[:, :2 * S].tolist() == g["expected_counts"]
     f = oracle.median_flags(med, cnt, S, g["threshold_bps"], 0, np.array(g["prev_flags"], dtype=np.uint8))
     assert f.tolist() == g["expected_flags"]
+
+
+# ---------------------------------------------------------------- per-host medians (§III.B.2)
+
+def _brute_bucket(rate: int) -> int:
+    # 10 kbps buckets, everything from 100 Mbps up in the last (bucket 10,000)
+    return min(rate // 10_000, 10_000)
+
+
+def _brute_host_rates(sites, local, n_sites, recs, bulk_bytes, filters=None):
+    out = {}
+    for src, dst, b, p, f, l in recs:
+        dur = (l - f) & 0xFFFFFFFF
+        if not brute.is_bulk(b, p, dur, bulk_bytes, filters):
+            continue
+        row = brute.row_of(sites, local, n_sites, src, dst)
+        if row >= 2 * n_sites:
+            continue
+        remote = src if row % 2 == 0 else dst
+        out.setdefault((remote << 32) | row, []).append(brute.rate_bps(b, dur))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_host_medians_match_brute(seed):
+    rng = np.random.default_rng(2600 + seed)
+    n_sites, sites, local = random_tiny_registry(rng, n_local=int(rng.integers(1, 4)))
+    recs = _rate_records(rng, int(rng.integers(0, 300)), sites, local)
+    recs += [recs[int(i)] for i in rng.integers(0, len(recs), size=len(recs))] if recs else []
+    bulk = int(rng.choice([0, 1_000_000]))
+    filters = _random_filters(rng) if rng.random() < 0.3 else None
+    rates = _brute_host_rates(sites, local, n_sites, recs, bulk, filters)
+    reg = _oracle_reg(sites, local, n_sites)
+    keys, med = oracle.host_medians(reg, soa(recs), bulk, filters)
+    assert sorted(rates) == keys.tolist()
+    # the lower median of the rates, then its bucket (buckets are monotone in the rate)
+    assert [_brute_bucket(statistics.median_low(rates[k])) for k in sorted(rates)] == med.tolist()
+
+
+def test_host_medians_bucket_array_definition():
+    """On a generated window: each host's median is where its bucket array's
+    cumulative count first reaches ceil(N/2) (the paper's bucket arrays, built
+    here per host with bincount), lies between the buckets of its minimum and
+    maximum rates, and the keys are host_stats'."""
+    reg = flowgen.registry_for(flowgen.PLAIN_LARGE)
+    rec = flowgen.records_for(flowgen.PLAIN_LARGE, reg=reg, n=300_000, stream=3)
+    o = oracle.Registry.from_generated(reg)
+    keys, med = oracle.host_medians(o, rec)
+    k2, st = oracle.host_stats(o, rec)
+    assert (keys == k2).all() and keys.size > 10_000
+    lo, hi = oracle.rate_bucket(st[:, 3]), oracle.rate_bucket(st[:, 4])
+    assert ((lo <= med) & (med <= hi)).all()
+    # per-host bucket arrays for the hosts with the most flows, and a sample of the rest
+    row, is_bulk, rate = oracle._classify_rows(o, rec, 1_000_000)
+    sel = is_bulk & (row < 2 * reg.n_sites)
+    remote = np.where(row % 2 == 0, rec.src_ip, rec.dst_ip)[sel]
+    key = (remote.astype(np.uint64) << np.uint64(32)) | row[sel].astype(np.uint64)
+    bucket = oracle.rate_bucket(rate[sel])
+    pick = list(np.argsort(-st[:, 0].astype(np.int64))[:20]) + \
+        list(np.random.default_rng(4).choice(keys.size, 200, replace=False))
+    for i in pick:
+        arr = np.bincount(bucket[key == keys[i]], minlength=10_001)
+        n = int(arr.sum())
+        assert n == int(st[i, 0])
+        assert int(np.argmax(np.cumsum(arr) >= (n + 1) // 2)) == int(med[i])
+    assert st[pick[0], 0] >= 10  # the busiest hosts hold many flows
+
+
+def test_host_worked_example():
+    g = load_golden("host_median_example.json")
+    sites = [(ip(a), l, s) for a, l, s in g["sites"]]
+    local = [(ip(a), l) for a, l in g["local"]]
+    recs = [(ip(r[0]), ip(r[1]), r[2], r[3], r[4], r[5]) for r in g["records"]]
+    reg = _oracle_reg(sites, local, g["n_sites"])
+    want_keys = [(ip(a) << 32) | row for a, row, _, _ in g["expected_hosts"]]
+    keys, st = oracle.host_stats(reg, soa(recs), g["bulk_bytes"])
+    assert keys.tolist() == want_keys
+    assert st.tolist() == [s for _, _, s, _ in g["expected_hosts"]]
+    keys, med = oracle.host_medians(reg, soa(recs), g["bulk_bytes"])
+    assert keys.tolist() == want_keys
+    assert med.tolist() == [m for _, _, _, m in g["expected_hosts"]]
+    # and the brute force agrees with the hand derivation
+    assert sorted(_brute_hosts(sites, local, g["n_sites"], recs, g["bulk_bytes"])) == want_keys
