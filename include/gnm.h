@@ -346,6 +346,32 @@ int gnm_classify_flag(const gnm_registry *reg, const gnm_records *rec, const uin
                       uint64_t min_bulk_flows, uint8_t *flags, hipStream_t stream);
 
 /*
+ * gnm_classify_flag_static — gnm_classify_flag for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors,
+ * except that the workspace is not the caller's: the per-workgroup partial
+ * tables live in a static device array of gnm_static_scratch_bytes() bytes
+ * (32 MiB) that the library holds on each GPU it runs on until the process
+ * ends.  The call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine); the array's device address is looked up once
+ * per device, on the first call made with that device current.
+ *   p->workspace    must be NULL (GNM_E_INVAL otherwise).
+ * A launch whose partial tables (gnm_workspace_bytes(reg, grid)) would pass
+ * the array's size is rejected with GNM_E_INVAL before anything is enqueued:
+ * lower p->grid_blocks.  Registries whose table does not fit LDS need no
+ * partial tables and are never rejected for size.  Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents: calls whose
+ * work overlaps on one GPU (concurrent streams, or graphs replayed
+ * concurrently) race on it and give unspecified tables.  Serialise them.
+ */
+int gnm_classify_flag_static(const gnm_registry *reg, const gnm_records *rec, const uint64_t *window_offsets,
+                             uint32_t n_windows, const gnm_params *p, gnm_acc *acc, uint64_t threshold_bps,
+                             uint64_t min_bulk_flows, uint8_t *flags, hipStream_t stream);
+
+/* Size in bytes of the static scratch array of gnm_classify_flag_static. */
+uint64_t gnm_static_scratch_bytes(void);
+
+/*
  * gnm_median_flags — the paper's warning criterion (§III.B.1, NetPerf
  * Monitoring Thread; §IV.B): a site is warned about when the median of its
  * transfer rates stays below a standard (1 Mbps) for two consecutive windows

@@ -37,7 +37,7 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
            "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_classify_aggregate",
-           "gnm_classify_flag", "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
+           "gnm_classify_flag", "gnm_classify_flag_static", "gnm_static_scratch_bytes", "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
            "gnm_netflow_v5_workspace_bytes", "gnm_netflow_v5_decode",
            "gnm_strerror", "gnm_last_error", "gnm_version")
 TUNE_MAX = 16
@@ -179,6 +179,10 @@ def lib():
         L.gnm_classify_flag.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32, ctypes.POINTER(Params), P,
                                         ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.gnm_classify_flag.restype = ctypes.c_int
+        L.gnm_classify_flag_static.argtypes = L.gnm_classify_flag.argtypes
+        L.gnm_classify_flag_static.restype = ctypes.c_int
+        L.gnm_static_scratch_bytes.argtypes = []
+        L.gnm_static_scratch_bytes.restype = ctypes.c_uint64
         L.gnm_flag_suboptimal.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P]
         L.gnm_flag_suboptimal.restype = ctypes.c_int
         L.gnm_median_flags.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, P, P, P, P]
@@ -428,6 +432,29 @@ def classify_flag(reg: Registry, rec, acc, flags, threshold_bps: int = 1_000_000
                                    ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()), int(threshold_bps),
                                    int(min_bulk_flows), ctypes.c_void_p(flags.data_ptr()),
                                    _stream_handle(stream)), "gnm_classify_flag")
+
+
+def classify_flag_static(reg: Registry, rec, acc, flags, threshold_bps: int = 1_000_000, min_bulk_flows: int = 0,
+                         window_offsets=None, n_windows: int = 1, bulk_bytes: int = 1_000_000,
+                         accumulate: bool = False, records_per_thread: int = 0, grid_blocks: int = 0, stream=None,
+                         n: Optional[int] = None, rate_hist=None, filters=None, hosts=None,
+                         flush_records: int = 0) -> None:
+    """gnm_classify_flag_static: gnm_classify_flag with its workspace in the
+    library's static device scratch (no workspace argument; the call allocates
+    nothing).  Calls whose work overlaps on one GPU race on that scratch."""
+    if flags.element_size() != 1 or flags.numel() < n_windows * reg.n_sites or not flags.is_cuda:
+        raise ValueError("flags must be a device uint8 tensor of n_windows * n_sites bytes")
+    c, off, p = _classify_args(reg, rec, acc, window_offsets, n_windows, bulk_bytes, accumulate, records_per_thread,
+                               grid_blocks, n, None, rate_hist, filters, hosts, flush_records)
+    _check(lib().gnm_classify_flag_static(reg.handle, ctypes.byref(c), ctypes.c_void_p(off), int(n_windows),
+                                          ctypes.byref(p), ctypes.c_void_p(acc.data_ptr()), int(threshold_bps),
+                                          int(min_bulk_flows), ctypes.c_void_p(flags.data_ptr()),
+                                          _stream_handle(stream)), "gnm_classify_flag_static")
+
+
+def static_scratch_bytes() -> int:
+    """gnm_static_scratch_bytes: size of the static scratch of classify_flag_static."""
+    return int(lib().gnm_static_scratch_bytes())
 
 
 def flag_suboptimal(reg: Registry, acc, n_windows: int, flags, threshold_bps: int = 1_000_000,

@@ -1271,6 +1271,18 @@ uint64_t partial_bytes(const gnm_registry *reg, uint64_t grid) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Workgroups of a classify launch over n records with R records per lane:
+// the caller's count, else one resident wave of workgroups (fewer for short
+// runs).
+uint64_t launch_grid(const gnm_registry *reg, uint64_t n, uint32_t R, uint32_t grid_blocks, int dev) {
+  const uint64_t resident = (uint64_t)device_cus(dev) * blocks_per_cu(reg);
+  const uint64_t tiles = (n + (uint64_t)kThreads * R - 1) / ((uint64_t)kThreads * R);
+  uint64_t grid = grid_blocks ? grid_blocks : (tiles < resident ? tiles : resident);
+  if (grid == 0) grid = 1;
+  if (grid > 65535u * 16u) grid = 65535u * 16u;
+  return grid;
+}
+
 }  // namespace
 }  // namespace gnm
 
@@ -1319,11 +1331,7 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   if (dev != reg->device) { set_last_error("registry belongs to another device"); return GNM_E_INVAL; }
 
   const uint64_t rows = reg->rows();
-  const uint64_t resident = (uint64_t)device_cus(dev) * blocks_per_cu(reg);
-  const uint64_t tiles = (rec->n + (uint64_t)kThreads * R - 1) / ((uint64_t)kThreads * R);
-  uint64_t grid = p.grid_blocks ? p.grid_blocks : (tiles < resident ? tiles : resident);
-  if (grid == 0) grid = 1;
-  if (grid > 65535u * 16u) grid = 65535u * 16u;
+  const uint64_t grid = launch_grid(reg, rec->n, R, p.grid_blocks, dev);
   if ((uint64_t)n_windows * rows * 8u > (uint64_t)INT32_MAX * 256u) {
     set_last_error("accumulator tables too large");
     return GNM_E_INVAL;
@@ -1550,4 +1558,80 @@ extern "C" int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hi
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "warn launch");
   return GNM_OK;
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+
+namespace gnm {
+
+// Workspace of gnm_classify_flag_static: the per-workgroup partial tables and
+// their window tags, in a file-scope device array.  Each GPU the library runs
+// on holds its own copy until the process ends; every call on that GPU shares
+// it.  Nothing in it needs to start at zero: each classify workgroup writes
+// its whole slot and tag before the reduce kernel reads them.
+constexpr uint64_t kStaticScratchBytes = 32ull << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on device dev, which must be the current
+// device: looked up once per device with hipGetSymbolAddress (in host code
+// the array's name is only a stand-in, never a device address).
+int static_scratch(int dev, void **out) {
+  static std::mutex mu;
+  static void *ptr[64] = {};
+  std::lock_guard<std::mutex> g(mu);
+  if (dev < 0 || dev >= 64) { set_last_error("device ordinal out of range"); return GNM_E_INVAL; }
+  if (!ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) { set_last_error("hipGetSymbolAddress(scratch) gave NULL"); return GNM_E_HIP; }
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return GNM_OK;
+}
+
+}  // namespace
+}  // namespace gnm
+
+extern "C" uint64_t gnm_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" int gnm_classify_flag_static(const gnm_registry *reg, const gnm_records *rec,
+                                        const uint64_t *window_offsets, uint32_t n_windows, const gnm_params *pp,
+                                        gnm_acc *acc, uint64_t threshold_bps, uint64_t min_bulk_flows,
+                                        uint8_t *flags, hipStream_t stream) {
+  if (!reg || !rec || !acc || !flags) { set_last_error("NULL argument"); return GNM_E_INVAL; }
+  if (reg->host_only) { set_last_error("registry was built host-only"); return GNM_E_UNSUPPORTED; }
+  if (pp && pp->workspace) {
+    set_last_error("gnm_classify_flag_static takes its workspace from the library's static scratch: "
+                   "p->workspace must be NULL");
+    return GNM_E_INVAL;
+  }
+  gnm_params p = pp ? *pp : gnm_params_default();
+  const uint32_t R = p.records_per_thread ? p.records_per_thread : 4u;
+  if (R != 1 && R != 2 && R != 4) { set_last_error("records_per_thread must be 0, 1, 2 or 4"); return GNM_E_INVAL; }
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != reg->device) { set_last_error("registry belongs to another device"); return GNM_E_INVAL; }
+  if (reg->acc_in_lds && rec->n > 0) {
+    const uint64_t grid = launch_grid(reg, rec->n, R, p.grid_blocks, dev);
+    const uint64_t need = partial_bytes(reg, grid);
+    if (need > kStaticScratchBytes) {
+      set_last_error("the partial tables of " + std::to_string(grid) + " workgroups x " +
+                     std::to_string(reg->rows()) + " rows need " + std::to_string(need) +
+                     " bytes; the static scratch holds " + std::to_string(kStaticScratchBytes) +
+                     " (lower grid_blocks)");
+      return GNM_E_INVAL;
+    }
+  }
+  void *ws = nullptr;
+  const int rc = static_scratch(dev, &ws);
+  if (rc != GNM_OK) return rc;
+  p.workspace = ws;
+  p.workspace_bytes = kStaticScratchBytes;
+  const FlagArgs fl{flags, threshold_bps, min_bulk_flows > 1 ? min_bulk_flows : 1, reg->n_sites};
+  return classify_impl(reg, rec, window_offsets, n_windows, &p, acc, fl, stream, true);
 }
