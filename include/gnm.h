@@ -123,24 +123,33 @@ typedef struct {
 #define GNM_RATE_BUCKET_BPS 10000u
 #define GNM_NO_MEDIAN 0xFFFFFFFFu /* median bucket of a row without bulk flows */
 
-/* Per-host statistics (§III.B.2, TransRate Kernel: transfer rates are also
- * computed for each host in a registered site).  An open-addressing table in
- * device memory, filled by the classify pass: one slot per (remote host,
- * direction) of a registered site seen with at least one bulk flow, keyed
- * by ((uint64_t)remote_address << 32) | (2*site + dir), where the remote
- * address is the source of an inbound flow and the destination of an
- * outbound one.  Per slot, stats[5*slot + f]: bulk flows, their bytes, rate
- * sum (modulo 2^64), rate minimum, rate maximum.  Slot positions depend on
- * timing; the set of (key, statistics) does not, while the table has room.
- * With several windows in one call the table covers all of them. */
-#define GNM_HOST_EMPTY 0xFFFFFFFFFFFFFFFFull /* key of a free slot */
+/* Per-host statistics (§III.B.2, TransRate Kernel: maximum, minimum,
+ * average and median transfer rates for each host in a registered site, the
+ * median read from the host's 10 kbps bucket array).  Filled by the classify
+ * call for every (remote host, direction) of a registered site with at least
+ * one bulk flow in the call's records (all windows of the call together),
+ * keyed by ((uint64_t)remote_address << 32) | (2*site + dir), where the
+ * remote address is the source of an inbound flow and the destination of an
+ * outbound one.  Host i of the call has key keys[i], statistics
+ * stats[5*i + f] (bulk flows, their bytes, rate sum (modulo 2^64), rate
+ * minimum, rate maximum) and median[i], the lower-median bucket of its N bulk
+ * flows' rates: the bucket of the ceil(N/2)-th smallest rate, buckets as for
+ * rate_hist (exact while a host has fewer than 2^32 bulk flows in a call).
+ * Hosts come in an order that depends on timing; the set of (key,
+ * statistics, median) does not.  The call never accumulates into the table
+ * (GNM_ACCUMULATE with hosts is GNM_E_INVAL), and needs fewer than 2^32
+ * records. */
 typedef struct {
-  uint64_t *keys;     /* DEVICE [capacity], 8-byte aligned */
-  uint64_t *stats;    /* DEVICE [capacity * 5], 8-byte aligned */
-  uint64_t capacity;  /* a power of two, at most 2^36 */
-  uint64_t *counters; /* DEVICE [2]: [0] slots in use after the call; [1] bulk flows left out because
-                         the 256 slots from their key's hash position were taken by other hosts
-                         (their hosts are then absent; a host present has all its flows) */
+  uint64_t *keys;      /* DEVICE [capacity], 8-byte aligned */
+  uint64_t *stats;     /* DEVICE [capacity * 5], 8-byte aligned */
+  uint32_t *median;    /* DEVICE [capacity], 4-byte aligned, or NULL (no medians written) */
+  uint64_t capacity;   /* hosts the arrays hold; more hosts than that: counters[0] still counts them all,
+                          and `capacity` of them (which ones depends on timing) are written */
+  uint64_t *counters;  /* DEVICE [2], 8-byte aligned, written by the call: [0] hosts found, [1] bulk flows
+                          of registered sites in the call */
+  void *work;          /* DEVICE scratch, 256-byte aligned, caller-owned: contents before and after a call
+                          do not matter; calls in flight must not share one */
+  uint64_t work_bytes; /* its size: at least gnm_host_work_bytes(reg, rec->n, grid_blocks) */
 } gnm_host_table;
 
 /* Per-call parameters.  Zero-initialise and set what you need;
@@ -169,9 +178,8 @@ typedef struct {
   uint32_t min_packets;          /* bulk only with packets >= min_packets */
   uint32_t min_duration_ms;      /* bulk only with dur >= min_duration_ms (dur > 0 is always required) */
   uint32_t reserved2;
-  const gnm_host_table *hosts;   /* optional per-host statistics (host pointer to a table description):
-                                    NULL = none; else filled by the same pass (cleared first unless
-                                    GNM_ACCUMULATE) */
+  const gnm_host_table *hosts;   /* optional per-host statistics and medians (host pointer to a table
+                                    description): NULL = none; else filled by the call */
 } gnm_params;
 
 #define GNM_REG_HOST_ONLY 0x1u   /* gnm_registry_opts.flags: build host structure only */
@@ -273,6 +281,17 @@ gnm_params gnm_params_default(void);
 uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks);
 
 /*
+ * gnm_host_work_bytes — size of the work buffer of a gnm_host_table for a
+ * classify call over n_records records on grid_blocks workgroups (0 = the
+ * automatic launch; it fits every automatic launch of up to n_records
+ * records).  The buffer holds one 32-byte entry per bulk flow of a
+ * registered site (room for every record) twice, to stage the flows and to
+ * order them by host partition, plus a partition count per workgroup: about
+ * 64 bytes per record.  0 for a NULL registry.
+ */
+uint64_t gnm_host_work_bytes(const gnm_registry *reg, uint64_t n_records, uint32_t grid_blocks);
+
+/*
  * gnm_classify_aggregate — §III.B.2 (TransRate Kernel) with the definition
  * above, for one or many windows in one launch.
  *   reg             registry built with a device upload.
@@ -297,14 +316,17 @@ uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks);
  * p->rate_hist, each bulk flow of a registered site also adds one to its
  * row's histogram with a device-scope 32-bit atomic; the caller owns the
  * histogram memory (n_windows * 2 * n_sites * GNM_RATE_BUCKETS * 4 bytes).
- * With p->hosts, each such flow also updates its host's slot (a device-scope
- * compare-and-swap to claim it, then five device-scope atomics), the table
- * is cleared first (unless accumulating) and its slots in use are counted
- * after the classify kernel.  Each classify workgroup walks a balanced contiguous slice of all
+ * With p->hosts, the classify kernel also stages each such flow (host key,
+ * bytes, rate) in p->hosts->work, and four kernels follow: partition counts
+ * by a hash of the key, their scan, the scatter into partition order, and one
+ * workgroup per partition that gathers the hosts' statistics and medians in
+ * LDS and writes them to the table.  Each classify workgroup walks a balanced contiguous slice of all
  * records, flushing its LDS table at window changes.  Errors: GNM_E_INVAL
  * (null pointers, n_windows = 0, offsets NULL with n_windows > 1,
  * records_per_thread not 0/1/2/4, n_windows tables beyond 2^39 words,
- * rate_hist not 16-byte aligned, a malformed host table), GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
+ * rate_hist not 16-byte aligned, a malformed host table or one with too
+ * small a work buffer, hosts with GNM_ACCUMULATE or with 2^32 records or
+ * more), GNM_E_UNSUPPORTED (host-only registry), GNM_E_HIP (launch failed).
  */
 int gnm_classify_aggregate(const gnm_registry *reg, const gnm_records *rec,
                            const uint64_t *window_offsets, uint32_t n_windows,

@@ -36,7 +36,7 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
-           "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_classify_aggregate",
+           "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_host_work_bytes", "gnm_classify_aggregate",
            "gnm_classify_flag", "gnm_classify_flag_static", "gnm_static_scratch_bytes", "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
            "gnm_netflow_v5_workspace_bytes", "gnm_netflow_v5_decode",
            "gnm_strerror", "gnm_last_error", "gnm_version")
@@ -75,37 +75,53 @@ class Params(ctypes.Structure):
 
 
 class HostTableC(ctypes.Structure):
-    _fields_ = [("keys", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
-                ("counters", ctypes.c_void_p)]
+    _fields_ = [("keys", ctypes.c_void_p), ("stats", ctypes.c_void_p), ("median", ctypes.c_void_p),
+                ("capacity", ctypes.c_uint64), ("counters", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("work_bytes", ctypes.c_uint64)]
 
 
-HOST_EMPTY = 0xFFFFFFFFFFFFFFFF
 HOST_FIELDS = ("bulk_flows", "bulk_bytes", "rate_sum_bps", "rate_min_bps", "rate_max_bps")
 
 
-class HostTable:
-    """Device per-host statistics table (gnm_host_table) of `capacity` slots (a power of two)."""
+def host_work_bytes(reg: "Registry", n_records: int, grid_blocks: int = 0) -> int:
+    """gnm_host_work_bytes: work buffer of a host table for n_records records."""
+    return int(lib().gnm_host_work_bytes(reg.handle, int(n_records), int(grid_blocks)))
 
-    def __init__(self, capacity: int, device=None):
+
+class HostTable:
+    """Device per-host statistics and medians (gnm_host_table) for calls of up
+    to n_records records on grid_blocks workgroups (0 = automatic): room for
+    `capacity` hosts, plus the work buffer."""
+
+    def __init__(self, reg: "Registry", capacity: int, n_records: int, grid_blocks: int = 0, device=None,
+                 medians: bool = True):
         import torch
         capacity = int(capacity)
-        if capacity <= 0 or capacity & (capacity - 1):
-            raise ValueError("capacity must be a power of two")
+        if capacity < 0:
+            raise ValueError("capacity must be >= 0")
         dev = device if device is not None else "cuda"
         self.capacity = capacity
-        self.keys = torch.empty(capacity, dtype=torch.int64, device=dev)
-        self.stats = torch.empty((capacity, 5), dtype=torch.int64, device=dev)
+        self.keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+        self.stats = torch.empty((max(capacity, 1), 5), dtype=torch.int64, device=dev)
+        self.median = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev) if medians else None
         self.counters = torch.zeros(2, dtype=torch.int64, device=dev)
-        self.c = HostTableC(self.keys.data_ptr(), self.stats.data_ptr(), capacity, self.counters.data_ptr())
+        wb = host_work_bytes(reg, n_records, grid_blocks)
+        self._work = torch.empty(wb + 256, dtype=torch.uint8, device=dev)
+        base = self._work.data_ptr()
+        self.c = HostTableC(self.keys.data_ptr(), self.stats.data_ptr(),
+                            self.median.data_ptr() if medians else 0, capacity, self.counters.data_ptr(),
+                            (base + 255) & ~255, wb)
 
     def to_numpy(self):
-        """(keys sorted ascending, stats [n, 5], hosts counted, flows left out), uint64."""
-        k = self.keys.cpu().numpy().view(np.uint64)
-        st = self.stats.cpu().numpy().view(np.uint64)
-        used = k != np.uint64(HOST_EMPTY)
-        order = np.argsort(k[used], kind="stable")
+        """(keys sorted ascending, stats [n, 5], median buckets (or None), hosts found, bulk flows of
+        registered sites); keys and stats uint64, medians uint32."""
         cnt = self.counters.cpu().numpy().view(np.uint64)
-        return k[used][order], st[used][order], int(cnt[0]), int(cnt[1])
+        n = min(int(cnt[0]), self.capacity)
+        k = self.keys[:n].cpu().numpy().view(np.uint64)
+        st = self.stats[:n].cpu().numpy().view(np.uint64)
+        order = np.argsort(k, kind="stable")
+        med = None if self.median is None else self.median[:n].cpu().numpy().view(np.uint32)[order]
+        return k[order], st[order], med, int(cnt[0]), int(cnt[1])
 
 
 FILTER_KEYS = ("min_avg_packet_bytes", "min_packets", "min_duration_ms")
@@ -173,6 +189,8 @@ def lib():
         L.gnm_params_default.restype = Params
         L.gnm_workspace_bytes.argtypes = [P, ctypes.c_uint32]
         L.gnm_workspace_bytes.restype = ctypes.c_uint64
+        L.gnm_host_work_bytes.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
+        L.gnm_host_work_bytes.restype = ctypes.c_uint64
         L.gnm_classify_aggregate.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32,
                                              ctypes.POINTER(Params), P, P]
         L.gnm_classify_aggregate.restype = ctypes.c_int

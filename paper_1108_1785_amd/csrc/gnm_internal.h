@@ -70,6 +70,9 @@ constexpr uint32_t kMaxLocalRanges = 32;
 constexpr uint32_t kLocalSubBlocks = 16;  // locality sub-blocks per root cell
 constexpr uint32_t kMaxSites = 1u << 28;
 constexpr uint32_t kLdsMax = 160u * 1024u;
+// LDS that every registry plan leaves free at the top of the 160 KB, for a
+// classify workgroup's counters (the per-host staging cursor)
+constexpr uint32_t kLdsReserve = 16u;
 
 // Accumulator table held in LDS by a classify workgroup: rows of kAccFields
 // 64-bit words (56 bytes, so rows fall on 32 distinct banks).  `cnt` packs

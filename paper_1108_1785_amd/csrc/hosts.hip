@@ -1,0 +1,486 @@
+// Per-host rate statistics and medians (§III.B.2, TransRate Kernel: maximum,
+// minimum, average and median transfer rates for each host in a registered
+// site, the median read from the host's 10 kbps bucket array).
+//
+// Dense bucket arrays per host do not fit (a 10 M-record window has about
+// half a million hosts with bulk flows; 10,001 buckets each would be 21 GB),
+// and hash-table updates with device-scope atomics are bound by the rate of
+// those atomics.  Here the classify kernel only appends one 32-byte entry
+// (host key, bytes, rate, bucket) per bulk flow of a registered site to its
+// workgroup's staging range, and four kernels finish the job with no
+// per-flow device atomics:
+//   1. host_count_kernel: per classify workgroup, the number of its entries
+//      in each of P partitions (a partition is the top bits of a hash of the
+//      key, so all entries of a host land in one partition);
+//   2. host_scan_kernel: for each partition, the offset of every workgroup's
+//      share within the partition (a column prefix sum) and the totals;
+//   3. host_scatter_kernel: every entry to its partition's range;
+//   4. host_reduce_kernel: one workgroup per partition gathers its hosts in
+//      an LDS hash map with their statistics (LDS atomics), then finds each
+//      host's lower median bucket (the ceil(N/2)-th smallest of its N flows'
+//      buckets) by a radix selection over the 14-bit bucket: four rounds,
+//      each counting the candidates' next 4-bit digit in 16 LDS bins per
+//      host and keeping the digit where the running count reaches the rank.
+//      A partition with more hosts than the map holds is done in batches: the
+//      entries of hosts not yet in the map are compacted in place and
+//      reduced by the next batch.
+// Each host is written once, at an index taken from counters[0]; the order
+// of hosts therefore depends on timing, the set of (key, statistics, median)
+// does not.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "gnm_device.h"
+#include "hosts.h"
+#include "registry.h"
+
+namespace gnm {
+
+namespace {
+
+constexpr uint32_t kHostThreads = 256;
+constexpr uint32_t kScanWaves = 16;         // host_scan_kernel: waves sharing one group of 64 partitions
+constexpr uint32_t kHostSlots = 256;        // LDS hash-map slots per reduce workgroup (a power of two)
+constexpr uint32_t kEntryCap = 2048;        // entries of a partition whose (slot, bucket) stay in LDS
+constexpr uint64_t kHostEmpty = ~0ull;      // free map slot (no key has all low 32 bits set)
+constexpr uint32_t kDigitBins = 16;         // radix selection: 4 bits per round
+constexpr uint32_t kDigitRounds = 4;        // buckets < 2^14: digits at bits 12, 8, 4, 0
+constexpr uint32_t kPartBitsMin = 6, kPartBitsMax = 14;
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t part_of(uint64_t key, uint32_t pbits) {
+  return (uint32_t)(mix64(key) >> (64u - pbits));
+}
+
+// Staged entries of classify workgroup b: [lo_b, lo_b + count[b]).
+__device__ __forceinline__ uint64_t slice_lo(uint32_t b, uint64_t n, uint32_t grid) {
+  return (uint64_t)b * n / grid;
+}
+
+struct Parts {
+  const HostEntry *stage;
+  const uint32_t *scount;
+  uint64_t n;
+  uint32_t grid, pbits;
+  uint32_t *phist;  // [grid][P]: counts, then each workgroup's offset within the partition
+  uint32_t *ptotal, *pbase;  // [P]
+  HostEntry *part;  // entries in partition order
+  u64 *keys, *stats;
+  uint32_t *median;
+  uint64_t capacity;
+  u64 *counters;
+};
+
+__device__ __forceinline__ void load_entry(const HostEntry *e, u64 &key, u64 &bytes, u64 &rate, uint32_t &bucket) {
+  const u64x2 a = *(const u64x2 *)e, b = *((const u64x2 *)e + 1);
+  key = a.x;
+  bytes = a.y;
+  rate = b.x;
+  bucket = (uint32_t)b.y;
+}
+
+__device__ __forceinline__ void store_entry(HostEntry *e, u64 key, u64 bytes, u64 rate, uint32_t bucket) {
+  *(u64x2 *)e = u64x2{key, bytes};
+  *((u64x2 *)e + 1) = u64x2{rate, (u64)bucket};
+}
+
+// Partition counts of classify workgroup b's entries (dynamic LDS: P
+// counters).  Workgroup 0 also clears the output counters.
+__global__ __launch_bounds__(kHostThreads) void host_count_kernel(const Parts q) {
+  extern __shared__ uint32_t h[];
+  const uint32_t P = 1u << q.pbits, b = blockIdx.x;
+  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) h[p] = 0u;
+  if (b == 0 && threadIdx.x == 0) {
+    q.counters[0] = 0;
+    q.counters[1] = 0;
+  }
+  __syncthreads();
+  const uint64_t lo = slice_lo(b, q.n, q.grid);
+  const uint32_t cnt = q.scount[b];
+  for (uint32_t i = threadIdx.x; i < cnt; i += kHostThreads)
+    atomicAdd(&h[part_of(q.stage[lo + i].key, q.pbits)], 1u);
+  __syncthreads();
+  uint32_t *row = q.phist + (uint64_t)b * P;
+  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) row[p] = h[p];
+}
+
+// Column prefix sums of the count matrix: workgroup x owns partitions
+// 64x .. 64x + 63 (lane j: partition 64x + j); its 16 waves each take a
+// sixteenth of the classify workgroups, sum their counts (8 loads in flight
+// per lane), meet in LDS, and then rewrite the counts as exclusive offsets.
+// Also the partition totals and the number of staged flows (counters[1]).
+__global__ __launch_bounds__(64 * kScanWaves) void host_scan_kernel(const Parts q) {
+  __shared__ uint32_t part[kScanWaves][64];
+  const uint32_t P = 1u << q.pbits, lane = threadIdx.x % 64u, w = threadIdx.x / 64u;
+  const uint32_t p = blockIdx.x * 64u + lane;
+  const uint32_t chunk = (q.grid + kScanWaves - 1u) / kScanWaves;
+  const uint32_t b0 = w * chunk < q.grid ? w * chunk : q.grid;
+  const uint32_t b1 = b0 + chunk < q.grid ? b0 + chunk : q.grid;
+  uint32_t s = 0;
+  for (uint32_t b = b0; b < b1; b += 8u) {
+    uint32_t v[8];
+#pragma unroll
+    for (uint32_t j = 0; j < 8u; ++j) v[j] = b + j < b1 ? q.phist[(uint64_t)(b + j) * P + p] : 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < 8u; ++j) s += v[j];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+  for (uint32_t v = 0; v < kScanWaves; ++v) {
+    run += v < w ? part[v][lane] : 0u;
+    total += part[v][lane];
+  }
+  for (uint32_t b = b0; b < b1; b += 8u) {
+    uint32_t v[8];
+#pragma unroll
+    for (uint32_t j = 0; j < 8u; ++j) v[j] = b + j < b1 ? q.phist[(uint64_t)(b + j) * P + p] : 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < 8u; ++j) {
+      if (b + j < b1) q.phist[(uint64_t)(b + j) * P + p] = run;
+      run += v[j];
+    }
+  }
+  if (w == 0) {
+    q.ptotal[p] = total;
+    u64 t = total;
+#pragma unroll
+    for (uint32_t o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0 && t) __hip_atomic_fetch_add(&q.counters[1], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Exclusive prefix sum of v[0..P) in LDS: every thread scans a run of
+// ceil(P / kHostThreads) consecutive values.
+__device__ void block_exclusive_scan(uint32_t *v, uint32_t P) {
+  __shared__ uint32_t wsum[kHostThreads / 64];
+  const uint32_t per = (P + kHostThreads - 1u) / kHostThreads;
+  const uint32_t start = threadIdx.x * per;
+  uint32_t s = 0;
+  for (uint32_t j = 0; j < per && start + j < P; ++j) s += v[start + j];
+  // inclusive scan of the thread sums over the workgroup
+  const uint32_t lane = threadIdx.x % 64u, w = threadIdx.x / 64u;
+  uint32_t x = s;
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63u) wsum[w] = x;
+  __syncthreads();
+  uint32_t before = x - s;
+  for (uint32_t v2 = 0; v2 < w; ++v2) before += wsum[v2];
+  uint32_t run = before;
+  for (uint32_t j = 0; j < per && start + j < P; ++j) {
+    const uint32_t c = v[start + j];
+    v[start + j] = run;
+    run += c;
+  }
+  __syncthreads();
+}
+
+// Every entry of classify workgroup b to its place in partition order: the
+// partition's base (a scan of the totals, recomputed by every workgroup in
+// LDS) plus b's offset within the partition, plus an LDS cursor.  Workgroup 0
+// also stores the bases for the reduce kernel.
+__global__ __launch_bounds__(kHostThreads) void host_scatter_kernel(const Parts q) {
+  extern __shared__ uint32_t cur[];
+  const uint32_t P = 1u << q.pbits, b = blockIdx.x;
+  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) cur[p] = q.ptotal[p];
+  __syncthreads();
+  block_exclusive_scan(cur, P);
+  if (b == 0)
+    for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) q.pbase[p] = cur[p];
+  const uint32_t *off = q.phist + (uint64_t)b * P;
+  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) cur[p] += off[p];
+  __syncthreads();
+  const uint64_t lo = slice_lo(b, q.n, q.grid);
+  const uint32_t cnt = q.scount[b];
+  for (uint32_t i = threadIdx.x; i < cnt; i += kHostThreads) {
+    u64 key, by, rt;
+    uint32_t bk;
+    load_entry(q.stage + lo + i, key, by, rt, bk);
+    const uint32_t pos = atomicAdd(&cur[part_of(key, q.pbits)], 1u);
+    store_entry(q.part + pos, key, by, rt, bk);
+  }
+}
+
+struct HostMap {
+  u64 key[kHostSlots];
+  u64 bytes[kHostSlots], rsum[kHostSlots], rmin[kHostSlots], rmax[kHostSlots];
+  uint32_t flows[kHostSlots];
+  uint32_t bins[kDigitBins][kHostSlots];  // digit counts, bin-major so a slot's walk is bank-conflict free
+  uint32_t want[kHostSlots];    // rank of the median among the candidates still in play
+  uint32_t prefix[kHostSlots];  // digits of the median bucket chosen so far
+  uint32_t out[kHostSlots];     // output index of the slot's host within the batch
+};
+
+__device__ __forceinline__ uint32_t slot_hash(u64 key) { return (uint32_t)mix64(key) & (kHostSlots - 1u); }
+
+// Slot of key in the map, inserting it when absent; kNoSlot when the map is
+// full.  Keys are never removed within a batch, so a slot seen holding
+// another key stays that way and linear probing needs no locks.
+__device__ __forceinline__ uint32_t map_insert(HostMap &m, u64 key) {
+  uint32_t s = slot_hash(key);
+  for (uint32_t probe = 0; probe < kHostSlots; ++probe) {
+    u64 cur = m.key[s];
+    if (cur == kHostEmpty) cur = atomicCAS(&m.key[s], kHostEmpty, key);
+    if (cur == kHostEmpty || cur == key) return s;
+    s = (s + 1u) & (kHostSlots - 1u);
+  }
+  return kNoSlot;
+}
+
+__device__ __forceinline__ uint32_t map_find(const HostMap &m, u64 key) {
+  uint32_t s = slot_hash(key);
+  for (uint32_t probe = 0; probe < kHostSlots; ++probe) {
+    const u64 cur = m.key[s];
+    if (cur == key) return s;
+    if (cur == kHostEmpty) return kNoSlot;
+    s = (s + 1u) & (kHostSlots - 1u);
+  }
+  return kNoSlot;
+}
+
+// Choose slot s's next digit: the bin where the running count of its
+// candidates reaches its rank (the rank becomes the rank within that bin),
+// from the 16 bins read at once; the bins are cleared for the next round.
+__device__ __forceinline__ void pick_digit(HostMap &m, uint32_t s) {
+  uint32_t b[kDigitBins];
+#pragma unroll
+  for (uint32_t j = 0; j < kDigitBins; ++j) b[j] = m.bins[j][s];
+  const uint32_t want = m.want[s];
+  uint32_t c = 0, d = 0, before = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kDigitBins - 1u; ++j) {
+    c += b[j];
+    const bool below = c < want;  // the target lies beyond bin j
+    d += below;
+    before = below ? c : before;
+  }
+  m.want[s] = want - before;
+  m.prefix[s] = (m.prefix[s] << 4) | d;
+#pragma unroll
+  for (uint32_t j = 0; j < kDigitBins; ++j) m.bins[j][s] = 0u;
+}
+
+constexpr uint32_t kPerThread = 4;  // entries a thread loads before working on them
+
+// One workgroup per partition.  A partition of at most kEntryCap entries
+// keeps each entry's (slot, bucket) in LDS after the first pass, so the
+// three later digit rounds read no device memory; a larger one (a hot host)
+// re-reads its entries and looks their keys up again.
+__global__ __launch_bounds__(kHostThreads) void host_reduce_kernel(const Parts q) {
+  static_assert(kHostSlots == kHostThreads, "one map slot per thread");
+  __shared__ HostMap m;
+  __shared__ uint32_t e_sb[kEntryCap];  // slot << 14 | bucket, kNoSlot for a host left to the next batch
+  __shared__ uint32_t s_overflow, s_deferred, s_wave[kHostThreads / 64];
+  __shared__ u64 s_out;
+  const uint32_t p = blockIdx.x, tid = threadIdx.x, lane = tid % 64u, wv = tid / 64u;
+  HostEntry *ent = q.part + q.pbase[p];
+  uint32_t n = q.ptotal[p];
+  while (n > 0) {
+    const bool in_lds = n <= kEntryCap;
+    m.key[tid] = kHostEmpty;
+    m.flows[tid] = 0u;
+    m.bytes[tid] = m.rsum[tid] = m.rmax[tid] = 0;
+    m.rmin[tid] = ~0ull;
+    m.prefix[tid] = 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < kDigitBins; ++j) m.bins[j][tid] = 0u;
+    if (tid == 0) {
+      s_overflow = 0u;
+      s_deferred = 0u;
+    }
+    __syncthreads();
+    // hosts, statistics and the first digit (bits 13..12) of every bucket;
+    // each thread loads kPerThread entries before it works on them
+    for (uint32_t i0 = 0; i0 < n; i0 += kPerThread * kHostThreads) {
+      u64 key[kPerThread], by[kPerThread], rt[kPerThread];
+      uint32_t bk[kPerThread];
+#pragma unroll
+      for (uint32_t j = 0; j < kPerThread; ++j) {
+        const uint32_t i = i0 + j * kHostThreads + tid;
+        if (i < n) load_entry(ent + i, key[j], by[j], rt[j], bk[j]);
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kPerThread; ++j) {
+        const uint32_t i = i0 + j * kHostThreads + tid;
+        if (i >= n) continue;
+        const uint32_t s = map_insert(m, key[j]);
+        if (in_lds) e_sb[i] = s == kNoSlot ? kNoSlot : (s << 14) | bk[j];
+        if (s == kNoSlot) {
+          s_overflow = 1u;
+          continue;
+        }
+        atomicAdd(&m.flows[s], 1u);
+        atomicAdd(&m.bytes[s], (u64)by[j]);
+        atomicAdd(&m.rsum[s], (u64)rt[j]);
+        atomicMin(&m.rmin[s], (u64)rt[j]);
+        atomicMax(&m.rmax[s], (u64)rt[j]);
+        atomicAdd(&m.bins[bk[j] >> 12][s], 1u);
+      }
+    }
+    __syncthreads();
+    // reserve the batch's output indexes now, so the atomic's round trip
+    // overlaps the digit rounds
+    const bool used = m.key[tid] != kHostEmpty;
+    const u64 bal = __ballot(used);
+    if (lane == 0) s_wave[wv] = (uint32_t)__popcll(bal);
+    if (used) m.want[tid] = (m.flows[tid] + 1u) / 2u;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t t = 0;
+      for (uint32_t v = 0; v < kHostThreads / 64u; ++v) {
+        const uint32_t c = s_wave[v];
+        s_wave[v] = t;
+        t += c;
+      }
+      s_out = t ? __hip_atomic_fetch_add(&q.counters[0], (u64)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+    }
+    if (used) {
+      pick_digit(m, tid);
+      m.out[tid] = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));  // plus s_wave[wv], known after the barrier
+    }
+    __syncthreads();
+    // the other three digits, among the candidates that share the digits so far
+    for (uint32_t r = 1; r < kDigitRounds; ++r) {
+      const uint32_t shift = 12u - 4u * r;
+      for (uint32_t i = tid; i < n; i += kHostThreads) {
+        uint32_t s, bk;
+        if (in_lds) {
+          const uint32_t sb = e_sb[i];
+          s = sb == kNoSlot ? kNoSlot : sb >> 14;
+          bk = sb & 0x3FFFu;
+        } else {
+          u64 key, by, rate;
+          load_entry(ent + i, key, by, rate, bk);
+          s = map_find(m, key);
+        }
+        if (s == kNoSlot) continue;
+        if ((bk >> (shift + 4u)) == m.prefix[s]) atomicAdd(&m.bins[(bk >> shift) & 15u][s], 1u);
+      }
+      __syncthreads();
+      if (used) pick_digit(m, tid);
+      __syncthreads();
+    }
+    // write the batch's hosts
+    if (used) {
+      const uint64_t idx = s_out + s_wave[wv] + m.out[tid];
+      if (idx < q.capacity) {
+        q.keys[idx] = m.key[tid];
+        u64 *st = q.stats + idx * 5u;
+        st[0] = m.flows[tid];
+        st[1] = m.bytes[tid];
+        st[2] = m.rsum[tid];
+        st[3] = m.rmin[tid];
+        st[4] = m.rmax[tid];
+        if (q.median) q.median[idx] = m.prefix[tid];
+      }
+    }
+    if (!s_overflow) break;
+    // entries of hosts that found no slot, compacted to the front for the
+    // next batch: each round reads a block of entries, waits, then writes
+    // them at or before the block's end, so no entry is overwritten unread
+    for (uint32_t i0 = 0; i0 < n; i0 += kHostThreads) {
+      const uint32_t i = i0 + tid;
+      u64 key = 0, by = 0, rt = 0;
+      uint32_t bk = 0;
+      bool keep = false;
+      if (i < n) {
+        load_entry(ent + i, key, by, rt, bk);
+        keep = in_lds ? e_sb[i] == kNoSlot : map_find(m, key) == kNoSlot;
+      }
+      __syncthreads();
+      if (keep) store_entry(ent + atomicAdd(&s_deferred, 1u), key, by, rt, bk);
+      __syncthreads();
+    }
+    n = s_deferred;
+    __syncthreads();
+  }
+}
+
+// n == 0: no classify launch and no entries; the counters still start at 0.
+__global__ void host_clear_kernel(u64 *counters) {
+  counters[0] = 0;
+  counters[1] = 0;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255u) & ~255ull; }
+
+struct Layout {
+  uint64_t stage, scount, phist, ptotal, pbase, part, end;
+};
+
+Layout layout(uint64_t n, uint64_t grid) {
+  const uint64_t P = 1ull << host_part_bits(n);
+  Layout L{};
+  uint64_t o = 0;
+  L.stage = o; o = align256(o + sizeof(HostEntry) * n);
+  L.scount = o; o = align256(o + 4u * grid);
+  L.phist = o; o = align256(o + 4u * grid * P);
+  L.ptotal = o; o = align256(o + 4u * P);
+  L.pbase = o; o = align256(o + 4u * P);
+  L.part = o; o = align256(o + sizeof(HostEntry) * n);
+  L.end = o;
+  return L;
+}
+
+}  // namespace
+
+uint32_t host_part_bits(uint64_t n) {
+  // the power of two nearest n / 2048: a generated window's partitions then
+  // hold about 300 entries of about 130 hosts, half the LDS map
+  uint32_t b = kPartBitsMin;
+  while (b < kPartBitsMax && (1ull << b) * 2896u <= n) ++b;
+  return b;
+}
+
+uint64_t host_work_bytes(uint64_t n, uint64_t grid) { return layout(n, grid).end; }
+
+HostStage host_stage(void *work, uint64_t n, uint64_t grid) {
+  const Layout L = layout(n, grid);
+  char *w = (char *)work;
+  return HostStage{(HostEntry *)(w + L.stage), (uint32_t *)(w + L.scount)};
+}
+
+int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, hipStream_t stream) {
+  if (n == 0) {
+    hipLaunchKernelGGL(host_clear_kernel, dim3(1), dim3(1), 0, stream, (u64 *)ht->counters);
+  } else {
+    const Layout L = layout(n, grid);
+    char *w = (char *)ht->work;
+    Parts q{};
+    q.stage = (const HostEntry *)(w + L.stage);
+    q.scount = (const uint32_t *)(w + L.scount);
+    q.n = n;
+    q.grid = (uint32_t)grid;
+    q.pbits = host_part_bits(n);
+    q.phist = (uint32_t *)(w + L.phist);
+    q.ptotal = (uint32_t *)(w + L.ptotal);
+    q.pbase = (uint32_t *)(w + L.pbase);
+    q.part = (HostEntry *)(w + L.part);
+    q.keys = (u64 *)ht->keys;
+    q.stats = (u64 *)ht->stats;
+    q.median = ht->median;
+    q.capacity = ht->capacity;
+    q.counters = (u64 *)ht->counters;
+    const uint32_t P = 1u << q.pbits;
+    hipLaunchKernelGGL(host_count_kernel, dim3((uint32_t)grid), dim3(kHostThreads), P * 4u, stream, q);
+    hipLaunchKernelGGL(host_scan_kernel, dim3(P / 64u), dim3(64 * kScanWaves), 0, stream, q);
+    hipLaunchKernelGGL(host_scatter_kernel, dim3((uint32_t)grid), dim3(kHostThreads), P * 4u, stream, q);
+    hipLaunchKernelGGL(host_reduce_kernel, dim3(P), dim3(kHostThreads), 0, stream, q);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_last_error(std::string("per-host kernels: ") + hipGetErrorString(e));
+    return GNM_E_HIP;
+  }
+  return GNM_OK;
+}
+
+}  // namespace gnm

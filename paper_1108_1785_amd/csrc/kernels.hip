@@ -40,11 +40,12 @@
 #include <mutex>
 #include <string>
 
+#include "gnm_device.h"
+#include "hosts.h"
 #include "registry.h"
 
 namespace gnm {
 
-typedef unsigned long long u64;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 // Pointers into the global address space (not flat).
@@ -56,13 +57,8 @@ constexpr uint32_t kRedRows = 8;     // reduce kernel: table rows (4 sites) per 
 constexpr uint32_t kRedWords = kRedRows * kAccFields;  // reduce kernel: 56 table words, one per lane
 constexpr uint32_t kRedGroups = 16;  // reduce kernel: at most 16 waves, each summing every G-th slot
 constexpr uint32_t kRedUnroll = 8;   // reduce kernel: slot loads in flight per lane
-constexpr uint32_t kBuckets = 10001;      // rate histogram: 10 kbps buckets, the last for > 100 Mbps
-constexpr uint32_t kBucketBps = 10000;
 constexpr uint32_t kFeatHist = 1;         // classify_kernel FEAT bits: rate histograms,
 constexpr uint32_t kFeatHosts = 2;        //   per-host statistics
-constexpr uint64_t kHostEmpty = ~0ull;    // free slot of the host table
-constexpr uint32_t kHostFields = 5;       // host statistics: bulk flows, bytes, rate sum, min, max
-constexpr uint32_t kHostMaxProbes = 256;  // slots a flow tries from its hash position
 constexpr uint32_t kHistKeyBits = 14;     // LDS histogram cache key: row << 14 | bucket
 constexpr uint32_t kHistSlotsMax = 4096;  // LDS histogram cache slots (8 bytes each, 4-way sets)
 constexpr uint32_t kMedWaves = 4;         // median kernel: waves sharing one (window, site) item
@@ -101,10 +97,9 @@ struct ClassifyArgs {
   uint32_t *hist;      // rate histograms: n_windows * hist_rows * kBuckets counts (FEAT & kFeatHist)
   uint32_t hist_rows;  // 2 * n_sites: rows of registered sites
   uint32_t lds_off_hist, hist_slots;  // LDS histogram cache (0 slots: every count goes to device memory)
-  u64 *host_keys;                     // host table (FEAT & kFeatHosts): keys,
-  u64 *host_stats;                    //   and 5 statistics words per slot
-  uint64_t host_mask;                 // capacity - 1 (a power of two)
-  u64 *host_counters;                 // [0] hosts (written by the count kernel), [1] flows left out
+  HostEntry *hs_entry;                // per-host staging (FEAT & kFeatHosts): workgroup b's entries
+  uint32_t *hs_count;                 //   at [lo_b, lo_b + hs_count[b]) of its record slice [lo_b, hi_b)
+  uint32_t lds_off_hcur;              // LDS word: the workgroup's staging cursor
   uint32_t filters;                   // any exclusion filter set
   uint32_t min_avg_packet_bytes, min_packets, min_duration_ms;
   LocalRanges local;
@@ -323,6 +318,8 @@ struct Lds {
   uint32_t *htags;  // histogram cache: key + 1 of the owner, 0 = free
   uint32_t *hcnt;   // histogram cache: counts
   uint32_t hslots;  // histogram cache slots (0 = none)
+  uint32_t *hcur;   // per-host staging: entries this workgroup has staged
+  HostEntry *se;    // per-host staging: this workgroup's range
 };
 
 // Staging code of a record whose row lives in an LDS cache slot.
@@ -642,50 +639,31 @@ __device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyAr
   for (int k = 0; k < R; ++k) row[k] = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
 }
 
-// Finalizer of splitmix64: spreads the host keys over the table.
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-  x ^= x >> 30;
-  x *= 0xBF58476D1CE4E5B9ull;
-  x ^= x >> 27;
-  x *= 0x94D049BB133111EBull;
-  return x ^ (x >> 31);
-}
-
-// Add one bulk flow to the host table (open addressing, linear probing over
-// the key array).  A slot's key is claimed with a device-scope
-// compare-and-swap and never changes afterwards, so a non-empty key read with
-// a plain load is current; an empty one may be stale, which the
-// compare-and-swap settles.  When the 256 slots from the key's hash position
-// are all taken by other hosts the flow is counted as left out (slots are
-// never freed, so the host's later flows are left out too, and a host in the
-// table has all its flows).  The bound keeps a full table from costing a
-// walk over every slot per flow.  (Keys and statistics in one 64-byte slot measured
-// the same here and cost more to clear and count: the six device-scope
-// operations per flow set the pace.)
-__device__ __forceinline__ void host_add(const ClassifyArgs &a, uint64_t key, uint64_t bytes, uint64_t rate) {
-  uint64_t h = mix64(key) & a.host_mask;
-  const uint64_t probes = a.host_mask < kHostMaxProbes ? a.host_mask + 1u : kHostMaxProbes;
-  for (uint64_t probe = 0; probe < probes; ++probe) {
-    uint64_t cur = a.host_keys[h];
-    if (cur == kHostEmpty) cur = atomicCAS(&a.host_keys[h], (u64)kHostEmpty, (u64)key);
-    if (cur == kHostEmpty || cur == key) {
-      u64 *st = a.host_stats + h * kHostFields;
-      __hip_atomic_fetch_add(&st[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&st[1], (u64)bytes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&st[2], (u64)rate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      atomicMin(&st[3], (u64)rate);
-      atomicMax(&st[4], (u64)rate);
-      return;
-    }
-    h = (h + 1u) & a.host_mask;
+// Per-host staging of a tile: the wave's entries for all R record slots are
+// reserved with one LDS atomic before the rates are computed (the bulk test
+// and the row decide which records have one), so each entry can be written
+// as soon as its rate is known.  hb[k]: the wave's lanes with an entry in
+// slot k; returns the first entry of slot 0.  Called by the whole wave.
+template <int R>
+__device__ __forceinline__ uint32_t reserve_hosts(const Lds &L, const bool (&want)[R], uint64_t (&hb)[R]) {
+  uint32_t total = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    hb[k] = __builtin_amdgcn_ballot_w64(want[k]);
+    total += (uint32_t)__builtin_popcountll(hb[k]);
   }
-  __hip_atomic_fetch_add(&a.host_counters[1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (total == 0u) return 0u;
+  uint32_t base = 0;
+  if (__lane_id() == (uint32_t)__builtin_ctzll(__builtin_amdgcn_read_exec())) base = atomicAdd(L.hcur, total);
+  return __builtin_amdgcn_readfirstlane(base);
 }
 
-// Histogram bucket of a rate: floor(rate / 10 kbps), at most the last bucket.
-__device__ __forceinline__ uint32_t rate_bucket(uint64_t rate) {
-  constexpr uint64_t kTop = (uint64_t)kBucketBps * (kBuckets - 1u);  // 100 Mbps
-  return rate >= kTop ? kBuckets - 1u : (uint32_t)rate / kBucketBps;
+// One staged entry: two 16-byte stores.
+__device__ __forceinline__ void stage_host(const Lds &L, uint32_t pos, uint64_t key, uint64_t bytes, uint64_t rate) {
+  typedef u64 u64x2_ __attribute__((ext_vector_type(2)));
+  u64x2_ *e = (u64x2_ *)(L.se + pos);
+  e[0] = u64x2_{(u64)key, (u64)bytes};
+  e[1] = u64x2_{(u64)rate, (u64)rate_bucket(rate)};
 }
 
 // Aggregate the tile's classified records.
@@ -694,6 +672,8 @@ __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t 
                                                const ClassifyArgs &a, const Lds &L, u64 *g_tab,
                                                uint32_t *h_tab) {
   const bool(&valid)[R] = t.v;
+  uint32_t durv[R];
+  bool bulkv[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const uint32_t dur = r.l[k] - r.f[k];
@@ -704,6 +684,25 @@ __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t 
     if (a.filters)
       bulk = bulk & (r.b[k] >= (uint64_t)a.min_avg_packet_bytes * r.pk[k]) & (r.pk[k] >= a.min_packets) &
              (dur >= a.min_duration_ms);
+    durv[k] = dur;
+    bulkv[k] = bulk;
+  }
+  // per-host statistics: bulk flows of registered sites (not the "no site"
+  // rows or NODIR), keyed by the remote endpoint (the source of an inbound
+  // flow, the destination of an outbound one)
+  uint64_t hb[R];
+  uint32_t hpos = 0;
+  if (FEAT & kFeatHosts) {
+    bool want[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) want[k] = bulkv[k] & (row[k] < a.hist_rows);
+    hpos = reserve_hosts<R>(L, want, hb);
+  }
+  const uint64_t below = (1ull << __lane_id()) - 1ull;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const uint32_t dur = durv[k];
+    const bool bulk = bulkv[k];
     uint32_t code = row[k];
     // (a spare LDS row for invalid records instead of this branch measured
     // 10 % slower on the 64-site registry)
@@ -711,14 +710,13 @@ __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t 
     if (bulk) {
       const uint64_t rate = rate_bps(r.b[k], dur);
       add_rate<ACC_LDS>(L, g_tab, code, rate);
-      // count in the row's histogram: registered sites only (not the
-      // "no site" rows or NODIR)
+      // count in the row's histogram: registered sites only
       if ((FEAT & kFeatHist) && row[k] < a.hist_rows) hist_add(L, h_tab, row[k], rate_bucket(rate));
-      // per-host statistics: the remote endpoint (the source of an inbound
-      // flow, the destination of an outbound one) of a registered site
       if ((FEAT & kFeatHosts) && row[k] < a.hist_rows)
-        host_add(a, ((uint64_t)((row[k] & 1u) ? t.d[k] : t.s[k]) << 32) | row[k], r.b[k], rate);
+        stage_host(L, hpos + (uint32_t)__builtin_popcountll(hb[k] & below),
+                   ((uint64_t)((row[k] & 1u) ? t.d[k] : t.s[k]) << 32) | row[k], r.b[k], rate);
     }
+    if (FEAT & kFeatHosts) hpos += (uint32_t)__builtin_popcountll(hb[k]);
   }
 }
 
@@ -760,43 +758,6 @@ __global__ void init_acc_kernel(u64 *__restrict__ acc, uint64_t words) {
   if (i < words) acc[i] = ((i & 7u) == 6u) ? ~0ull : 0ull;
 }
 
-// Host table: free every slot (key empty, statistics zero, minimum at the
-// maximum), grid-stride.
-__global__ void host_init_kernel(u64 *__restrict__ keys, u64 *__restrict__ stats, uint64_t cap) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
-    keys[i] = kHostEmpty;
-    u64 *st = stats + i * kHostFields;
-    st[0] = 0;
-    st[1] = 0;
-    st[2] = 0;
-    st[3] = ~0ull;
-    st[4] = 0;
-  }
-}
-
-// counters[0] = 0, and counters[1] = 0 too unless accumulating.
-__global__ void host_reset_kernel(u64 *counters, uint32_t accumulate) {
-  counters[0] = 0;
-  if (!accumulate) counters[1] = 0;
-}
-
-// counters[0] += slots in use: a few hundred workgroups, each summing in LDS
-// and adding once (device-scope atomics on one address serialise).
-__global__ __launch_bounds__(256) void host_count_kernel(const u64 *__restrict__ keys, uint64_t cap, u64 *counters) {
-  __shared__ u64 part[4];
-  u64 c = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x)
-    c += keys[i] != kHostEmpty;
-#pragma unroll
-  for (uint32_t o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if (threadIdx.x % 64u == 0u) part[threadIdx.x / 64u] = c;
-  __syncthreads();
-  if (threadIdx.x == 0u) {
-    const u64 t = part[0] + part[1] + part[2] + part[3];
-    if (t) __hip_atomic_fetch_add(&counters[0], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
 // Zero n 32-bit words at a 16-byte aligned address: four per lane, grid-stride.
 __global__ void zero_words_kernel(uint32_t *__restrict__ p, uint64_t n) {
   const uint64_t quads = (n + 3u) / 4u;
@@ -834,18 +795,22 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   const uint32_t hslots = HIST ? a.hist_slots : 0u;
   uint32_t *s_htags = (uint32_t *)(lds + a.lds_off_hist);
   for (uint32_t i = tid; i < 2u * hslots; i += kThreads) s_htags[i] = 0u;  // tags, then counts
+  constexpr bool HOSTS = (FEAT & kFeatHosts) != 0;
+  uint32_t *s_hcur = (uint32_t *)(lds + a.lds_off_hcur);
+  if (HOSTS && tid == 0) *s_hcur = 0u;
   __syncthreads();
-  const Lds L{s_root, s_lines, s_acc, s_tags, slots, s_htags, s_htags + hslots, hslots};
-
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
   const uint64_t hi = (uint64_t)(blockIdx.x + 1) * a.n / gridDim.x;
+  const Lds L{s_root, s_lines, s_acc, s_tags, slots, s_htags, s_htags + hslots, hslots, s_hcur,
+              HOSTS ? a.hs_entry + lo : nullptr};
   if (lo == hi) {
     // empty slice: leave an empty table whose window keeps the slots ordered
     if (ACC_LDS && a.ws) {
       uint64_t we;
       flush_partial(a, s_acc, window_of(a, lo ? lo - 1 : 0, we));
     }
+    if (HOSTS && tid == 0) a.hs_count[blockIdx.x] = 0u;
     return;
   }
   uint64_t i = lo;
@@ -881,6 +846,10 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     }
     if (HIST && hslots) flush_hist(L, h_tab);
     i = seg_end;
+  }
+  if (HOSTS) {
+    __syncthreads();
+    if (tid == 0) a.hs_count[blockIdx.x] = *s_hcur;
   }
 }
 
@@ -1294,6 +1263,13 @@ extern "C" gnm_params gnm_params_default(void) {
   return p;
 }
 
+extern "C" uint64_t gnm_host_work_bytes(const gnm_registry *reg, uint64_t n_records, uint32_t grid_blocks) {
+  if (!reg) return 0;
+  // an automatic launch uses at most one resident wave of workgroups
+  const uint64_t grid = grid_blocks ? grid_blocks : (uint64_t)device_cus(reg->device) * blocks_per_cu(reg);
+  return host_work_bytes(n_records, grid);
+}
+
 extern "C" uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks) {
   if (!reg) return 0;
   const uint64_t grid = grid_blocks ? grid_blocks : (uint64_t)device_cus(reg->device) * blocks_per_cu(reg);
@@ -1342,11 +1318,26 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     return GNM_E_INVAL;
   }
   const gnm_host_table *ht = p.hosts;
-  if (ht && (!ht->keys || !ht->stats || !ht->counters || ht->capacity == 0 ||
-             (ht->capacity & (ht->capacity - 1)) != 0 || ht->capacity > (1ull << 36) ||
-             ((uintptr_t)ht->keys & 7u) || ((uintptr_t)ht->stats & 7u) || ((uintptr_t)ht->counters & 7u))) {
-    set_last_error("host table: NULL or misaligned arrays, or a capacity that is not a power of two up to 2^36");
-    return GNM_E_INVAL;
+  if (ht) {
+    if ((ht->capacity && (!ht->keys || !ht->stats)) || !ht->counters || !ht->work ||
+        ((uintptr_t)ht->keys & 7u) || ((uintptr_t)ht->stats & 7u) || ((uintptr_t)ht->counters & 7u) ||
+        ((uintptr_t)ht->median & 3u) || ((uintptr_t)ht->work & 255u)) {
+      set_last_error("host table: NULL or misaligned arrays or work buffer");
+      return GNM_E_INVAL;
+    }
+    if (p.flags & GNM_ACCUMULATE) {
+      set_last_error("per-host statistics cover one call's records: GNM_ACCUMULATE cannot be combined with hosts");
+      return GNM_E_INVAL;
+    }
+    if (rec->n >= (1ull << 32)) {
+      set_last_error("per-host statistics need fewer than 2^32 records per call");
+      return GNM_E_INVAL;
+    }
+    if (ht->work_bytes < host_work_bytes(rec->n, grid)) {
+      set_last_error("host table: work buffer of " + std::to_string(ht->work_bytes) + " bytes, " +
+                     std::to_string(host_work_bytes(rec->n, grid)) + " needed (gnm_host_work_bytes)");
+      return GNM_E_INVAL;
+    }
   }
   const uint64_t row_tiles = (rows + kRedRows - 1) / kRedRows;
   const bool use_ws = rec->n > 0 && reg->acc_in_lds && p.workspace &&
@@ -1374,23 +1365,27 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   a.hist = p.rate_hist;
   a.hist_rows = 2u * reg->n_sites;
   if (ht) {
-    a.host_keys = (u64 *)ht->keys;
-    a.host_stats = (u64 *)ht->stats;
-    a.host_mask = ht->capacity - 1u;
-    a.host_counters = (u64 *)ht->counters;
+    const HostStage st = host_stage(ht->work, rec->n, grid);
+    a.hs_entry = st.entry;
+    a.hs_count = st.count;
   }
   uint32_t lds_launch = reg->lds_bytes;
   if (p.rate_hist) {
     // the histogram cache takes the LDS the registry leaves free, within the
     // budget that keeps the registry's workgroups per CU
     const uint32_t off = (reg->lds_bytes + 15u) & ~15u;
-    const uint32_t budget = reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax;
+    const uint32_t budget = (reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax) - kLdsReserve;
     uint32_t hs = budget > off ? (budget - off) / 8u : 0u;
     hs = (hs < kHistSlotsMax ? hs : kHistSlotsMax) & ~3u;
     if (hs < 64u) hs = 0;
     a.lds_off_hist = off;
     a.hist_slots = hs;
     lds_launch = off + hs * 8u;
+  }
+  if (ht) {
+    // the staging cursor: one word in the bytes every LDS plan leaves free
+    a.lds_off_hcur = (lds_launch + 15u) & ~15u;
+    lds_launch = a.lds_off_hcur + 16u;
   }
   if (use_ws) {
     a.ws = (u64 *)p.workspace;
@@ -1420,17 +1415,6 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "init launch");
   }
-  if (ht) {
-    hipLaunchKernelGGL(host_reset_kernel, dim3(1), dim3(1), 0, stream, (u64 *)ht->counters,
-                       (p.flags & GNM_ACCUMULATE) ? 1u : 0u);
-    if (!(p.flags & GNM_ACCUMULATE)) {
-      const uint64_t cap = (uint64_t)device_cus(dev) * 64u, blocks = (ht->capacity + 255u) / 256u;
-      hipLaunchKernelGGL(host_init_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(256), 0, stream,
-                         (u64 *)ht->keys, (u64 *)ht->stats, ht->capacity);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "host table init launch");
-  }
   if (p.rate_hist && !(p.flags & GNM_ACCUMULATE)) {
     const uint64_t quads = (hist_words + 3u) / 4u;
     const uint64_t cap = (uint64_t)device_cus(dev) * 64u;
@@ -1440,14 +1424,10 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "histogram init launch");
   }
-  // slots in use, counted after the classify launch (and on an empty run)
+  // the per-host kernels, after the classify launch (and on an empty run)
   auto count_hosts = [&]() -> int {
     if (!ht) return GNM_OK;
-    const uint64_t cap = (uint64_t)device_cus(dev) * 2u, blocks = (ht->capacity + 255u) / 256u;
-    hipLaunchKernelGGL(host_count_kernel, dim3((uint32_t)(blocks < cap ? blocks : cap)), dim3(256), 0, stream,
-                       (const u64 *)ht->keys, ht->capacity, (u64 *)ht->counters);
-    const hipError_t e2 = hipGetLastError();
-    return e2 == hipSuccess ? GNM_OK : hip_fail(e2, "host count launch");
+    return host_pipeline_launch(ht, rec->n, grid, stream);
   };
   // the mean-rate flags, when the reduce kernel does not apply them
   auto flag_launch = [&]() -> int {

@@ -296,7 +296,9 @@ void build_local_masks(gnm_registry *r) {
 // LDS plan for a classify workgroup: the root (with locality masks), then (if
 // it fits) the accumulator table, then (if they fit) the leaf lines.
 void plan_lds(gnm_registry *r, uint32_t lds_budget) {
-  // The budget covers root, accumulator table (or its cache) and leaf lines.
+  // The budget covers root, accumulator table (or its cache) and leaf lines;
+  // the top kLdsReserve bytes of LDS stay free.
+  if (lds_budget > kLdsMax - kLdsReserve) lds_budget = kLdsMax - kLdsReserve;
   const uint64_t root_b = 8ull << r->root_bits;
   const uint64_t line_b = 4ull * r->lines.size();
   const uint64_t acc_b = 8ull * kAccFields * r->rows();

@@ -222,7 +222,7 @@ def test_filter_params_checked():
 
 def test_new_binding_arguments_checked_on_the_host():
     with pytest.raises(ValueError):
-        gnm.HostTable(1000)            # not a power of two, rejected before any allocation
+        gnm.HostTable(None, -1, 1000)  # a negative capacity, rejected before any allocation
     with pytest.raises(ValueError):
         gnm.make_params(hosts=object())
     with pytest.raises(ValueError):
@@ -241,3 +241,13 @@ def test_gnm_params_layout_matches_header():
     assert p.bulk_bytes == 1_000_000 and p.flags == 0 and not p.rate_hist and not p.hosts
     assert (p.min_avg_packet_bytes, p.min_packets, p.min_duration_ms) == (0, 0, 0)
     assert ctypes.sizeof(gnm.Params) == 8 + 4 * 4 + 8 + 8 + 8 + 4 * 4 + 8
+
+
+def test_host_work_bytes():
+    # two staged copies of a 32-byte entry per record, plus per-workgroup partition counts
+    reg = gnm.Registry([0x0B000000], [8], [0], 1, [0x0A000000], [16], host_only=True)
+    assert gnm.host_work_bytes(reg, 0, 256) > 0
+    for n in (1, 1000, 10_000_000):
+        w1, w2 = gnm.host_work_bytes(reg, n, 256), gnm.host_work_bytes(reg, n, 512)
+        assert 64 * n <= w1 < w2 <= 64 * n + 512 * 4 * 16384 + 8 * 16384 + 4096
+    assert gnm.lib().gnm_host_work_bytes(None, 100, 1) == 0

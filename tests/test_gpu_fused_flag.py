@@ -211,7 +211,7 @@ def test_fused_flag_with_histograms_hosts_and_filters(torch_cuda):
         acc = torch.empty((1, reg.rows, 8), dtype=torch.int64, device=DEV)
         flags = torch.full((n_sites,), 0xA5, dtype=torch.uint8, device=DEV)
         hist = gnm.make_rate_hist(reg, 1)
-        hosts = gnm.HostTable(1 << 16, device=DEV)
+        hosts = gnm.HostTable(reg, 1 << 16, rec.n, device=DEV)
         gnm.classify_flag(reg, to_device(rec), acc, flags, thr, 0, n=rec.n, rate_hist=hist, hosts=hosts, filters=f,
                           workspace=gnm.make_workspace(reg) if ws else None)
         torch.cuda.synchronize()
@@ -221,6 +221,7 @@ def test_fused_flag_with_histograms_hosts_and_filters(torch_cuda):
         S2 = 2 * n_sites
         h = hist.cpu().numpy().view(np.uint32).reshape(1, S2, -1)
         assert (h == oracle.rate_histograms(s["orc"], rec, filters=f)[:, :S2]).all()
-        keys, st, used, dropped = hosts.to_numpy()
+        keys, st, med, found, _ = hosts.to_numpy()
         ek, es = oracle.host_stats(s["orc"], rec, filters=f)
-        assert dropped == 0 and used == keys.size and (keys == ek).all() and (st == es).all()
+        _, em = oracle.host_medians(s["orc"], rec, filters=f)
+        assert found == keys.size and (keys == ek).all() and (st == es).all() and (med == em).all()
