@@ -670,9 +670,10 @@ def main():
             nw5 = len(table_parts)
             acc5 = torch.empty((nw5, reg5.rows, 8), dtype=torch.int64, device=dev)
             flags5 = torch.empty(nw5 * reg5_h.n_sites, dtype=torch.uint8, device=dev)
-            ws5 = tune.tuning_workspace(reg5, device=dev)
+            ws5 = tune.tuning_workspace(reg5, device=dev, n_records=big5.n, n_windows=nw5)
             tp5 = tune.tuned_params(reg5, s5, acc5, window_offsets=off5, n_windows=nw5, n=big5.n, workspace=ws5)
-            ws5 = gnm.make_workspace(reg5, tp5["grid_blocks"], device=dev)
+            del ws5
+            ws5 = gnm.make_workspace(reg5, tp5["grid_blocks"], device=dev, n_records=big5.n, n_windows=nw5)
             g5 = gnm.Graph(reg5, s5, acc5, window_offsets=off5, n_windows=nw5, flags=flags5,
                            records_per_thread=tp5["records_per_thread"], grid_blocks=tp5["grid_blocks"],
                            workspace=ws5)

@@ -281,6 +281,25 @@ gnm_params gnm_params_default(void);
 uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks);
 
 /*
+ * gnm_workspace_bytes_n — size of the classify workspace for a call over
+ * n_records records in n_windows windows on grid_blocks workgroups (0 = the
+ * automatic launch; the size fits every automatic launch of up to n_records
+ * records).  For a registry whose table fits LDS it is gnm_workspace_bytes.
+ * For one whose table does not (gnm_registry_info.acc_in_lds == 0), the
+ * workspace holds the spilled rows instead: the rows that miss a workgroup's
+ * LDS row cache and the cached rows flushed at window changes are staged as
+ * 64-byte partial rows (at most one per record, and twice: staged, then in
+ * partition order) and merged by one workgroup per (window, 256 table rows),
+ * which writes its rows of the table and their flag bytes without
+ * device-scope atomics: about 128 bytes per record.  Without that workspace
+ * the rows go to the table with device-scope atomics, with the same results.
+ * 0 for a NULL registry, n_windows = 0, or more than 16,384 (window, 256-row)
+ * ranges (such calls always use the atomics).
+ */
+uint64_t gnm_workspace_bytes_n(const gnm_registry *reg, uint64_t n_records, uint32_t n_windows,
+                               uint32_t grid_blocks);
+
+/*
  * gnm_host_work_bytes — size of the work buffer of a gnm_host_table for a
  * classify call over n_records records on grid_blocks workgroups (0 = the
  * automatic launch; it fits every automatic launch of up to n_records

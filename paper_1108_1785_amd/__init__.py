@@ -36,7 +36,7 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
-           "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_host_work_bytes", "gnm_classify_aggregate",
+           "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_workspace_bytes_n", "gnm_host_work_bytes", "gnm_classify_aggregate",
            "gnm_classify_flag", "gnm_classify_flag_static", "gnm_static_scratch_bytes", "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
            "gnm_netflow_v5_workspace_bytes", "gnm_netflow_v5_decode",
            "gnm_strerror", "gnm_last_error", "gnm_version")
@@ -189,6 +189,8 @@ def lib():
         L.gnm_params_default.restype = Params
         L.gnm_workspace_bytes.argtypes = [P, ctypes.c_uint32]
         L.gnm_workspace_bytes.restype = ctypes.c_uint64
+        L.gnm_workspace_bytes_n.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.gnm_workspace_bytes_n.restype = ctypes.c_uint64
         L.gnm_host_work_bytes.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
         L.gnm_host_work_bytes.restype = ctypes.c_uint64
         L.gnm_classify_aggregate.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32,
@@ -392,11 +394,23 @@ def workspace_bytes(reg: Registry, grid_blocks: int = 0) -> int:
     return int(lib().gnm_workspace_bytes(reg.handle, int(grid_blocks)))
 
 
-def make_workspace(reg: Registry, grid_blocks: int = 0, device=None):
-    """A device byte tensor of gnm_workspace_bytes(reg, grid_blocks) bytes."""
+def workspace_bytes_n(reg: Registry, n_records: int, n_windows: int = 1, grid_blocks: int = 0) -> int:
+    """gnm_workspace_bytes_n: scratch size for a call over n_records records in n_windows windows."""
+    return int(lib().gnm_workspace_bytes_n(reg.handle, int(n_records), int(n_windows), int(grid_blocks)))
+
+
+def make_workspace(reg: Registry, grid_blocks: int = 0, device=None, n_records: Optional[int] = None,
+                   n_windows: int = 1):
+    """A device byte tensor of gnm_workspace_bytes(reg, grid_blocks) bytes, or, with
+    n_records, of gnm_workspace_bytes_n (which also holds the spilled rows of a
+    table too large for LDS); 256-byte aligned (torch's allocations are)."""
     import torch
-    return torch.empty(workspace_bytes(reg, grid_blocks), dtype=torch.uint8,
-                       device=device if device is not None else "cuda")
+    nb = workspace_bytes(reg, grid_blocks) if n_records is None else \
+        workspace_bytes_n(reg, n_records, n_windows, grid_blocks)
+    t = torch.empty(max(nb, 1), dtype=torch.uint8, device=device if device is not None else "cuda")
+    if t.data_ptr() % 256:
+        raise RuntimeError("device allocation not 256-byte aligned")
+    return t
 
 
 def classify_aggregate(reg: Registry, rec, acc, window_offsets=None, n_windows: int = 1,

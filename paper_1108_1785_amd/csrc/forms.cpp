@@ -130,7 +130,7 @@ extern "C" int gnm_autotune(const gnm_registry *reg, const gnm_records *rec, con
       if (n >= GNM_TUNE_MAX) break;
       // with a workspace, only shapes whose partial tables fit it: every
       // candidate then merges the same way as the tuned launch will
-      if (b.workspace && reg->acc_in_lds && gnm_workspace_bytes(reg, grid) > b.workspace_bytes) continue;
+      if (b.workspace && gnm_workspace_bytes_n(reg, rec->n, n_windows, grid) > b.workspace_bytes) continue;
       gnm_params p = b;
       p.records_per_thread = rpt;
       p.grid_blocks = grid;

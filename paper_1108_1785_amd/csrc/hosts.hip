@@ -34,6 +34,7 @@
 
 #include "gnm_device.h"
 #include "hosts.h"
+#include "partition.h"
 #include "registry.h"
 
 namespace gnm {
@@ -41,7 +42,6 @@ namespace gnm {
 namespace {
 
 constexpr uint32_t kHostThreads = 256;
-constexpr uint32_t kScanWaves = 16;         // host_scan_kernel: waves sharing one group of 64 partitions
 constexpr uint32_t kHostSlots = 256;        // LDS hash-map slots per reduce workgroup (a power of two)
 constexpr uint32_t kEntryCap = 2048;        // entries of a partition whose (slot, bucket) stay in LDS
 constexpr uint64_t kHostEmpty = ~0ull;      // free map slot (no key has all low 32 bits set)
@@ -52,23 +52,18 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
 typedef u64 u64x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ uint32_t part_of(uint64_t key, uint32_t pbits) {
-  return (uint32_t)(mix64(key) >> (64u - pbits));
-}
-
-// Staged entries of classify workgroup b: [lo_b, lo_b + count[b]).
-__device__ __forceinline__ uint64_t slice_lo(uint32_t b, uint64_t n, uint32_t grid) {
-  return (uint64_t)b * n / grid;
-}
+// Partition of a host entry: the top pbits of a hash of its key, so all
+// entries of a host land in one partition.
+struct HostPart {
+  uint32_t pbits;
+  static __device__ __forceinline__ uint32_t part(const HostEntry &e, const HostPart &t) {
+    return (uint32_t)(mix64(e.key) >> (64u - t.pbits));
+  }
+};
 
 struct Parts {
-  const HostEntry *stage;
-  const uint32_t *scount;
-  uint64_t n;
-  uint32_t grid, pbits;
-  uint32_t *phist;  // [grid][P]: counts, then each workgroup's offset within the partition
-  uint32_t *ptotal, *pbase;  // [P]
-  HostEntry *part;  // entries in partition order
+  HostEntry *part;
+  const uint32_t *ptotal, *pbase;
   u64 *keys, *stats;
   uint32_t *median;
   uint64_t capacity;
@@ -86,127 +81,6 @@ __device__ __forceinline__ void load_entry(const HostEntry *e, u64 &key, u64 &by
 __device__ __forceinline__ void store_entry(HostEntry *e, u64 key, u64 bytes, u64 rate, uint32_t bucket) {
   *(u64x2 *)e = u64x2{key, bytes};
   *((u64x2 *)e + 1) = u64x2{rate, (u64)bucket};
-}
-
-// Partition counts of classify workgroup b's entries (dynamic LDS: P
-// counters).  Workgroup 0 also clears the output counters.
-__global__ __launch_bounds__(kHostThreads) void host_count_kernel(const Parts q) {
-  extern __shared__ uint32_t h[];
-  const uint32_t P = 1u << q.pbits, b = blockIdx.x;
-  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) h[p] = 0u;
-  if (b == 0 && threadIdx.x == 0) {
-    q.counters[0] = 0;
-    q.counters[1] = 0;
-  }
-  __syncthreads();
-  const uint64_t lo = slice_lo(b, q.n, q.grid);
-  const uint32_t cnt = q.scount[b];
-  for (uint32_t i = threadIdx.x; i < cnt; i += kHostThreads)
-    atomicAdd(&h[part_of(q.stage[lo + i].key, q.pbits)], 1u);
-  __syncthreads();
-  uint32_t *row = q.phist + (uint64_t)b * P;
-  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) row[p] = h[p];
-}
-
-// Column prefix sums of the count matrix: workgroup x owns partitions
-// 64x .. 64x + 63 (lane j: partition 64x + j); its 16 waves each take a
-// sixteenth of the classify workgroups, sum their counts (8 loads in flight
-// per lane), meet in LDS, and then rewrite the counts as exclusive offsets.
-// Also the partition totals and the number of staged flows (counters[1]).
-__global__ __launch_bounds__(64 * kScanWaves) void host_scan_kernel(const Parts q) {
-  __shared__ uint32_t part[kScanWaves][64];
-  const uint32_t P = 1u << q.pbits, lane = threadIdx.x % 64u, w = threadIdx.x / 64u;
-  const uint32_t p = blockIdx.x * 64u + lane;
-  const uint32_t chunk = (q.grid + kScanWaves - 1u) / kScanWaves;
-  const uint32_t b0 = w * chunk < q.grid ? w * chunk : q.grid;
-  const uint32_t b1 = b0 + chunk < q.grid ? b0 + chunk : q.grid;
-  uint32_t s = 0;
-  for (uint32_t b = b0; b < b1; b += 8u) {
-    uint32_t v[8];
-#pragma unroll
-    for (uint32_t j = 0; j < 8u; ++j) v[j] = b + j < b1 ? q.phist[(uint64_t)(b + j) * P + p] : 0u;
-#pragma unroll
-    for (uint32_t j = 0; j < 8u; ++j) s += v[j];
-  }
-  part[w][lane] = s;
-  __syncthreads();
-  uint32_t run = 0, total = 0;
-  for (uint32_t v = 0; v < kScanWaves; ++v) {
-    run += v < w ? part[v][lane] : 0u;
-    total += part[v][lane];
-  }
-  for (uint32_t b = b0; b < b1; b += 8u) {
-    uint32_t v[8];
-#pragma unroll
-    for (uint32_t j = 0; j < 8u; ++j) v[j] = b + j < b1 ? q.phist[(uint64_t)(b + j) * P + p] : 0u;
-#pragma unroll
-    for (uint32_t j = 0; j < 8u; ++j) {
-      if (b + j < b1) q.phist[(uint64_t)(b + j) * P + p] = run;
-      run += v[j];
-    }
-  }
-  if (w == 0) {
-    q.ptotal[p] = total;
-    u64 t = total;
-#pragma unroll
-    for (uint32_t o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if (lane == 0 && t) __hip_atomic_fetch_add(&q.counters[1], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Exclusive prefix sum of v[0..P) in LDS: every thread scans a run of
-// ceil(P / kHostThreads) consecutive values.
-__device__ void block_exclusive_scan(uint32_t *v, uint32_t P) {
-  __shared__ uint32_t wsum[kHostThreads / 64];
-  const uint32_t per = (P + kHostThreads - 1u) / kHostThreads;
-  const uint32_t start = threadIdx.x * per;
-  uint32_t s = 0;
-  for (uint32_t j = 0; j < per && start + j < P; ++j) s += v[start + j];
-  // inclusive scan of the thread sums over the workgroup
-  const uint32_t lane = threadIdx.x % 64u, w = threadIdx.x / 64u;
-  uint32_t x = s;
-#pragma unroll
-  for (uint32_t o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63u) wsum[w] = x;
-  __syncthreads();
-  uint32_t before = x - s;
-  for (uint32_t v2 = 0; v2 < w; ++v2) before += wsum[v2];
-  uint32_t run = before;
-  for (uint32_t j = 0; j < per && start + j < P; ++j) {
-    const uint32_t c = v[start + j];
-    v[start + j] = run;
-    run += c;
-  }
-  __syncthreads();
-}
-
-// Every entry of classify workgroup b to its place in partition order: the
-// partition's base (a scan of the totals, recomputed by every workgroup in
-// LDS) plus b's offset within the partition, plus an LDS cursor.  Workgroup 0
-// also stores the bases for the reduce kernel.
-__global__ __launch_bounds__(kHostThreads) void host_scatter_kernel(const Parts q) {
-  extern __shared__ uint32_t cur[];
-  const uint32_t P = 1u << q.pbits, b = blockIdx.x;
-  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) cur[p] = q.ptotal[p];
-  __syncthreads();
-  block_exclusive_scan(cur, P);
-  if (b == 0)
-    for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) q.pbase[p] = cur[p];
-  const uint32_t *off = q.phist + (uint64_t)b * P;
-  for (uint32_t p = threadIdx.x; p < P; p += kHostThreads) cur[p] += off[p];
-  __syncthreads();
-  const uint64_t lo = slice_lo(b, q.n, q.grid);
-  const uint32_t cnt = q.scount[b];
-  for (uint32_t i = threadIdx.x; i < cnt; i += kHostThreads) {
-    u64 key, by, rt;
-    uint32_t bk;
-    load_entry(q.stage + lo + i, key, by, rt, bk);
-    const uint32_t pos = atomicAdd(&cur[part_of(key, q.pbits)], 1u);
-    store_entry(q.part + pos, key, by, rt, bk);
-  }
 }
 
 struct HostMap {
@@ -410,24 +284,8 @@ __global__ void host_clear_kernel(u64 *counters) {
   counters[1] = 0;
 }
 
-uint64_t align256(uint64_t x) { return (x + 255u) & ~255ull; }
-
-struct Layout {
-  uint64_t stage, scount, phist, ptotal, pbase, part, end;
-};
-
-Layout layout(uint64_t n, uint64_t grid) {
-  const uint64_t P = 1ull << host_part_bits(n);
-  Layout L{};
-  uint64_t o = 0;
-  L.stage = o; o = align256(o + sizeof(HostEntry) * n);
-  L.scount = o; o = align256(o + 4u * grid);
-  L.phist = o; o = align256(o + 4u * grid * P);
-  L.ptotal = o; o = align256(o + 4u * P);
-  L.pbase = o; o = align256(o + 4u * P);
-  L.part = o; o = align256(o + sizeof(HostEntry) * n);
-  L.end = o;
-  return L;
+PartLayout layout(uint64_t n, uint64_t grid) {
+  return part_layout(n, grid, 1ull << host_part_bits(n), sizeof(HostEntry));
 }
 
 }  // namespace
@@ -443,7 +301,7 @@ uint32_t host_part_bits(uint64_t n) {
 uint64_t host_work_bytes(uint64_t n, uint64_t grid) { return layout(n, grid).end; }
 
 HostStage host_stage(void *work, uint64_t n, uint64_t grid) {
-  const Layout L = layout(n, grid);
+  const PartLayout L = layout(n, grid);
   char *w = (char *)work;
   return HostStage{(HostEntry *)(w + L.stage), (uint32_t *)(w + L.scount)};
 }
@@ -452,27 +310,37 @@ int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, hi
   if (n == 0) {
     hipLaunchKernelGGL(host_clear_kernel, dim3(1), dim3(1), 0, stream, (u64 *)ht->counters);
   } else {
-    const Layout L = layout(n, grid);
+    const PartLayout L = layout(n, grid);
     char *w = (char *)ht->work;
+    PartArgs<HostEntry> pa{};
+    pa.stage = (const HostEntry *)(w + L.stage);
+    pa.scount = (const uint32_t *)(w + L.scount);
+    pa.n = n;
+    pa.grid = (uint32_t)grid;
+    const HostPart hp{host_part_bits(n)};
+    pa.nparts = 1u << hp.pbits;
+    pa.phist = (uint32_t *)(w + L.phist);
+    pa.ptotal = (uint32_t *)(w + L.ptotal);
+    pa.pbase = (uint32_t *)(w + L.pbase);
+    pa.part = (HostEntry *)(w + L.part);
+    pa.staged = (u64 *)ht->counters + 1;
+    pa.clear = (u64 *)ht->counters;
+    pa.nclear = 2;
     Parts q{};
-    q.stage = (const HostEntry *)(w + L.stage);
-    q.scount = (const uint32_t *)(w + L.scount);
-    q.n = n;
-    q.grid = (uint32_t)grid;
-    q.pbits = host_part_bits(n);
-    q.phist = (uint32_t *)(w + L.phist);
-    q.ptotal = (uint32_t *)(w + L.ptotal);
-    q.pbase = (uint32_t *)(w + L.pbase);
-    q.part = (HostEntry *)(w + L.part);
+    q.part = pa.part;
+    q.ptotal = pa.ptotal;
+    q.pbase = pa.pbase;
     q.keys = (u64 *)ht->keys;
     q.stats = (u64 *)ht->stats;
     q.median = ht->median;
     q.capacity = ht->capacity;
     q.counters = (u64 *)ht->counters;
-    const uint32_t P = 1u << q.pbits;
-    hipLaunchKernelGGL(host_count_kernel, dim3((uint32_t)grid), dim3(kHostThreads), P * 4u, stream, q);
-    hipLaunchKernelGGL(host_scan_kernel, dim3(P / 64u), dim3(64 * kScanWaves), 0, stream, q);
-    hipLaunchKernelGGL(host_scatter_kernel, dim3((uint32_t)grid), dim3(kHostThreads), P * 4u, stream, q);
+    const uint32_t P = pa.nparts;
+    hipLaunchKernelGGL((part_count_kernel<HostEntry, HostPart>), dim3((uint32_t)grid), dim3(kPartThreads), P * 4u,
+                       stream, pa, hp);
+    hipLaunchKernelGGL((part_scan_kernel<HostEntry>), dim3(P / 64u), dim3(64 * kPartScanWaves), 0, stream, pa);
+    hipLaunchKernelGGL((part_scatter_kernel<HostEntry, HostPart>), dim3((uint32_t)grid), dim3(kPartThreads),
+                       P * 4u, stream, pa, hp);
     hipLaunchKernelGGL(host_reduce_kernel, dim3(P), dim3(kHostThreads), 0, stream, q);
   }
   const hipError_t e = hipGetLastError();

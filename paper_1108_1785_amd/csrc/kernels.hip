@@ -43,6 +43,7 @@
 #include "gnm_device.h"
 #include "hosts.h"
 #include "registry.h"
+#include "table.h"
 
 namespace gnm {
 
@@ -99,7 +100,10 @@ struct ClassifyArgs {
   uint32_t lds_off_hist, hist_slots;  // LDS histogram cache (0 slots: every count goes to device memory)
   HostEntry *hs_entry;                // per-host staging (FEAT & kFeatHosts): workgroup b's entries
   uint32_t *hs_count;                 //   at [lo_b, lo_b + hs_count[b]) of its record slice [lo_b, hi_b)
-  uint32_t lds_off_hcur;              // LDS word: the workgroup's staging cursor
+  TableEntry *ts_entry;               // spilled rows (a table beyond LDS, with a workspace; NULL: device
+  uint32_t *ts_count;                 //   atomics): workgroup b's entries at [s_b, s_b + ts_count[b]),
+  uint32_t ts_extra;                  //   s_b = lo_b + b * ts_extra, room for hi_b - lo_b + ts_extra
+  uint32_t lds_off_ctr;               // LDS words: the workgroup's staging cursors (hosts, spilled rows)
   uint32_t filters;                   // any exclusion filter set
   uint32_t min_avg_packet_bytes, min_packets, min_duration_ms;
   LocalRanges local;
@@ -320,6 +324,9 @@ struct Lds {
   uint32_t hslots;  // histogram cache slots (0 = none)
   uint32_t *hcur;   // per-host staging: entries this workgroup has staged
   HostEntry *se;    // per-host staging: this workgroup's range
+  uint32_t *tcur;   // spilled rows: partial rows this workgroup has staged
+  TableEntry *te;   // spilled rows: this workgroup's range (NULL: misses and flushes use device atomics)
+  uint32_t win;     // window of the current segment
 };
 
 // Staging code of a record whose row lives in an LDS cache slot.
@@ -375,6 +382,7 @@ __device__ __forceinline__ uint32_t accumulate(const Lds &L, u64 *g_row, uint32_
     atomicAdd(&t[kDur], (u64)dur);
     return kInSlot | slot;
   }
+  if (L.te) return row;  // spilled: the caller stages the record as a partial row
   u64 *g = g_row + (uint64_t)row * 8u;
   atomicAdd(&g[0], 1ull);
   atomicAdd(&g[1], (u64)b);
@@ -470,10 +478,64 @@ __device__ __forceinline__ void flush_hist(const Lds &L, uint32_t *h) {
   __syncthreads();
 }
 
-// Flush the LDS cache slots into window table g with device-scope atomics and
-// free them.
-__device__ __forceinline__ void flush_cache(const Lds &L, u64 *__restrict__ g) {
+// One staged 32-byte entry of window L.win (two 16-byte stores).
+__device__ __forceinline__ void stage_entry(const Lds &L, uint32_t pos, uint32_t w, uint32_t row_kind, u64 x, u64 y,
+                                            u64 z) {
+  typedef u64 u64x2_ __attribute__((ext_vector_type(2)));
+  u64x2_ *e = (u64x2_ *)(L.te + pos);
+  e[0] = u64x2_{(u64)w | ((u64)row_kind << 32), x};
+  e[1] = u64x2_{y, z};
+}
+
+// Entries reserved for the wave's lanes with `want`: the first entry of the
+// wave's run (one LDS atomic by the first active lane); bal = the lanes.
+__device__ __forceinline__ uint32_t reserve_rows(uint32_t *cursor, bool want, uint64_t &bal, uint32_t per = 1u) {
+  bal = __builtin_amdgcn_ballot_w64(want);
+  if (!bal) return 0u;
+  uint32_t base = 0;
+  if (__lane_id() == (uint32_t)__builtin_ctzll(__builtin_amdgcn_read_exec()))
+    base = atomicAdd(cursor, per * (uint32_t)__builtin_popcountll(bal));
+  return __builtin_amdgcn_readfirstlane(base);
+}
+
+// Flush the LDS cache slots into window table g with device-scope atomics,
+// or, when the table spills and the workgroup's range has room for three
+// entries per claimed slot below `room`, stage them; then free them.
+__device__ __forceinline__ void flush_cache(const Lds &L, u64 *__restrict__ g, uint32_t room) {
   __syncthreads();
+  bool stage = false;
+  if (L.te) {
+    // claimed slots, counted by every wave into the spare LDS counter word
+    uint32_t *claimed = L.tcur + 1;
+    if (threadIdx.x == 0) *claimed = 0u;
+    __syncthreads();
+    uint32_t c = 0;
+    for (uint32_t sl = threadIdx.x; sl < L.slots; sl += kThreads) c += L.tags[sl] != 0u;
+    for (uint32_t o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (__lane_id() == 0 && c) atomicAdd(claimed, c);
+    __syncthreads();
+    stage = *L.tcur + 3u * *claimed <= room;
+  }
+  if (stage) {
+    const uint64_t below = (1ull << __lane_id()) - 1ull;
+    for (uint32_t s0 = 0; s0 < L.slots; s0 += kThreads) {  // whole waves, so the reservation is uniform
+      const uint32_t sl = s0 + threadIdx.x;
+      const uint32_t tag = sl < L.slots ? L.tags[sl] : 0u;
+      uint64_t bal;
+      const uint32_t base = reserve_rows(L.tcur, tag != 0u, bal, 3u);
+      if (tag == 0u) continue;
+      u64 *t = L.acc + sl * kAccFields;
+      const uint32_t pos = base + 3u * (uint32_t)__builtin_popcountll(bal & below), row = tag - 1u;
+      stage_entry(L, pos, L.win, row | (kRowA << kRowKindShift), t[kCnt], t[kBytes], t[kPackets]);
+      stage_entry(L, pos + 1u, L.win, row | (kRowB << kRowKindShift), t[kDur], t[kRateSum], t[kRateMin]);
+      stage_entry(L, pos + 2u, L.win, row | (kRowC << kRowKindShift), t[kRateMax], 0ull, 0ull);
+      t[kCnt] = t[kBytes] = t[kPackets] = t[kDur] = t[kRateSum] = t[kRateMax] = 0;
+      t[kRateMin] = ~0ull;
+      L.tags[sl] = 0u;
+    }
+    __syncthreads();
+    return;
+  }
   for (uint32_t sl = threadIdx.x; sl < L.slots; sl += kThreads) {
     const uint32_t tag = L.tags[sl];
     if (tag == 0u) continue;
@@ -707,9 +769,19 @@ __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t 
     // (a spare LDS row for invalid records instead of this branch measured
     // 10 % slower on the 64-site registry)
     if (valid[k]) code = accumulate<ACC_LDS>(L, g_tab, row[k], r.b[k], r.pk[k], dur, bulk);
+    // a spilled table: a record that missed the cache becomes a partial row
+    const bool spill = !ACC_LDS && L.te != nullptr;
+    const bool miss = spill && valid[k] && !(code & kInSlot);
+    uint64_t sbal = 0;
+    uint32_t sbase = 0;
+    if (spill) sbase = reserve_rows(L.tcur, miss, sbal);
+    uint64_t rate = 0;
+    if (bulk) rate = rate_bps(r.b[k], dur);
+    if (miss)
+      stage_entry(L, sbase + (uint32_t)__builtin_popcountll(sbal & below), L.win | (bulk ? kRecBulk : 0u),
+                  row[k] | (kRec << kRowKindShift), (u64)r.pk[k] | ((u64)dur << 32), r.b[k], rate);
     if (bulk) {
-      const uint64_t rate = rate_bps(r.b[k], dur);
-      add_rate<ACC_LDS>(L, g_tab, code, rate);
+      if (!miss) add_rate<ACC_LDS>(L, g_tab, code, rate);
       // count in the row's histogram: registered sites only
       if ((FEAT & kFeatHist) && row[k] < a.hist_rows) hist_add(L, h_tab, row[k], rate_bucket(rate));
       if ((FEAT & kFeatHosts) && row[k] < a.hist_rows)
@@ -796,14 +868,21 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   uint32_t *s_htags = (uint32_t *)(lds + a.lds_off_hist);
   for (uint32_t i = tid; i < 2u * hslots; i += kThreads) s_htags[i] = 0u;  // tags, then counts
   constexpr bool HOSTS = (FEAT & kFeatHosts) != 0;
-  uint32_t *s_hcur = (uint32_t *)(lds + a.lds_off_hcur);
-  if (HOSTS && tid == 0) *s_hcur = 0u;
+  const bool spill = !ACC_LDS && a.ts_entry != nullptr;
+  uint32_t *s_hcur = (uint32_t *)(lds + a.lds_off_ctr), *s_tcur = s_hcur + 1;
+  if ((HOSTS || spill) && tid == 0) {
+    s_hcur[0] = 0u;
+    s_tcur[0] = 0u;
+  }
   __syncthreads();
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
   const uint64_t hi = (uint64_t)(blockIdx.x + 1) * a.n / gridDim.x;
-  const Lds L{s_root, s_lines, s_acc, s_tags, slots, s_htags, s_htags + hslots, hslots, s_hcur,
-              HOSTS ? a.hs_entry + lo : nullptr};
+  Lds L{s_root, s_lines, s_acc, s_tags, slots, s_htags, s_htags + hslots, hslots, s_hcur,
+        HOSTS ? a.hs_entry + lo : nullptr, s_tcur, spill ? a.ts_entry + lo + (uint64_t)blockIdx.x * a.ts_extra : nullptr,
+        0u};
+  // spilled rows: the entries this workgroup's range holds
+  const uint32_t t_cap = (uint32_t)(hi - lo) + a.ts_extra;
   if (lo == hi) {
     // empty slice: leave an empty table whose window keeps the slots ordered
     if (ACC_LDS && a.ws) {
@@ -811,6 +890,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
       flush_partial(a, s_acc, window_of(a, lo ? lo - 1 : 0, we));
     }
     if (HOSTS && tid == 0) a.hs_count[blockIdx.x] = 0u;
+    if (spill && tid == 0) a.ts_count[blockIdx.x] = 0u;
     return;
   }
   uint64_t i = lo;
@@ -820,6 +900,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     uint64_t seg_end = wend < hi ? wend : hi;
     if (seg_end - i > a.flush_records) seg_end = i + a.flush_records;
     u64 *g_tab = a.acc + (uint64_t)w * rows * 8u;
+    L.win = w;
     uint32_t *h_tab = HIST ? a.hist + (uint64_t)w * a.hist_rows * kBuckets : nullptr;
 
     if (VEC) {
@@ -842,14 +923,17 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
       if (seg_end >= hi && a.ws) flush_partial(a, s_acc, w);
       else flush_atomic(s_acc, g_tab, rows);
     } else if (slots) {
-      flush_cache(L, g_tab);
+      // room for this flush: what the range holds less one entry for each
+      // record still to come
+      flush_cache(L, g_tab, t_cap - (uint32_t)(hi - seg_end));
     }
     if (HIST && hslots) flush_hist(L, h_tab);
     i = seg_end;
   }
-  if (HOSTS) {
+  if (HOSTS || spill) {
     __syncthreads();
-    if (tid == 0) a.hs_count[blockIdx.x] = *s_hcur;
+    if (HOSTS && tid == 0) a.hs_count[blockIdx.x] = *s_hcur;
+    if (spill && tid == 0) a.ts_count[blockIdx.x] = *s_tcur;
   }
 }
 
@@ -1270,6 +1354,15 @@ extern "C" uint64_t gnm_host_work_bytes(const gnm_registry *reg, uint64_t n_reco
   return host_work_bytes(n_records, grid);
 }
 
+extern "C" uint64_t gnm_workspace_bytes_n(const gnm_registry *reg, uint64_t n_records, uint32_t n_windows,
+                                          uint32_t grid_blocks) {
+  if (!reg) return 0;
+  const uint64_t grid = grid_blocks ? grid_blocks : (uint64_t)device_cus(reg->device) * blocks_per_cu(reg);
+  if (reg->acc_in_lds) return partial_bytes(reg, grid);
+  if (n_windows == 0 || !table_fits(n_windows, (uint32_t)reg->rows())) return 0;
+  return table_spill_bytes(n_records, grid, n_windows, (uint32_t)reg->rows(), reg->cache_slots);
+}
+
 extern "C" uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks) {
   if (!reg) return 0;
   const uint64_t grid = grid_blocks ? grid_blocks : (uint64_t)device_cus(reg->device) * blocks_per_cu(reg);
@@ -1382,10 +1475,22 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     a.hist_slots = hs;
     lds_launch = off + hs * 8u;
   }
-  if (ht) {
-    // the staging cursor: one word in the bytes every LDS plan leaves free
-    a.lds_off_hcur = (lds_launch + 15u) & ~15u;
-    lds_launch = a.lds_off_hcur + 16u;
+  // a table beyond LDS with a workspace that holds its spilled rows: the
+  // misses of the row cache and its flushes are staged and merged by the
+  // table kernels instead of device-scope atomics
+  const bool spill = !reg->acc_in_lds && rec->n > 0 && rec->n < (1ull << 32) && p.workspace &&
+                     ((uintptr_t)p.workspace & 255u) == 0 && table_fits(n_windows, (uint32_t)rows) &&
+                     p.workspace_bytes >= table_spill_bytes(rec->n, grid, n_windows, (uint32_t)rows, reg->cache_slots);
+  if (spill) {
+    const TableStage ts = table_stage(p.workspace, rec->n, grid, n_windows, (uint32_t)rows, reg->cache_slots);
+    a.ts_entry = ts.entry;
+    a.ts_count = ts.count;
+    a.ts_extra = (uint32_t)table_extra(reg->cache_slots);
+  }
+  if (ht || spill) {
+    // the staging cursors: words in the bytes every LDS plan leaves free
+    a.lds_off_ctr = (lds_launch + 15u) & ~15u;
+    lds_launch = a.lds_off_ctr + 16u;
   }
   if (use_ws) {
     a.ws = (u64 *)p.workspace;
@@ -1446,7 +1551,12 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kThreads), lds_launch, stream, a);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "classify launch");
-  if (use_ws) {
+  if (spill) {
+    const TableFlags tf{fl.flags, fl.threshold, fl.need, fl.n_sites};
+    const int rc = table_merge_launch(p.workspace, rec->n, grid, n_windows, (uint32_t)rows, reg->cache_slots,
+                                      (unsigned long long *)acc, tf, stream);
+    if (rc != GNM_OK) return rc;
+  } else if (use_ws) {
     // waves per reduce workgroup: enough for one round of kRedUnroll loads per
     // lane over the mean slots per window, rounded up to a power of two, at
     // most kRedGroups (smaller workgroups fit more per CU at once)

@@ -34,17 +34,20 @@ def workload_key(reg: Registry, n_records: int, n_windows: int, workspace_bytes:
     # sizes bucketed by powers of two: the best shape changes slowly with size
     nb = int(math.log2(max(n_records, 1)))
     wb = int(math.log2(max(n_windows, 1)))
-    # the merge path: atomics, or workspace partial tables for shapes up to
-    # the workgroup count the workspace holds (candidates beyond it are not timed)
-    merge = "atomic" if not workspace_bytes or not i["acc_in_lds"] else "ws%d" % max_grid_for(reg, workspace_bytes)
+    # the merge path: atomics, or the workspace (partial tables, or the
+    # spilled rows of a table beyond LDS) for shapes up to the workgroup count
+    # the workspace holds (candidates beyond it are not timed)
+    g = max_grid_for(reg, workspace_bytes, n_records, n_windows) if workspace_bytes else 0
+    merge = "atomic" if not g else ("ws%d" if i["acc_in_lds"] else "spill%d") % g
     return "%s|%s|%s|n2^%d|w2^%d|%s" % (_device_name(), version(), shape, nb, wb, merge)
 
 
-def max_grid_for(reg: Registry, workspace_bytes: int) -> int:
-    """Largest tuning candidate workgroup count whose partial tables fit workspace_bytes (0: none)."""
+def max_grid_for(reg: Registry, workspace_bytes: int, n_records: int = 0, n_windows: int = 1) -> int:
+    """Largest tuning candidate workgroup count whose workspace fits workspace_bytes (0: none)."""
     best = 0
     for g in candidate_grids(reg):
-        if workspace_bytes_for(reg, g) <= workspace_bytes:
+        need = workspace_bytes_for(reg, g, n_records, n_windows)
+        if need and need <= workspace_bytes:
             best = max(best, g)
     return best
 
@@ -61,16 +64,17 @@ def candidate_grids(reg: Registry):
     return [r, r // 2, 2 * r, 4 * r]
 
 
-def workspace_bytes_for(reg: Registry, grid: int) -> int:
-    from . import workspace_bytes
-    return workspace_bytes(reg, grid)
+def workspace_bytes_for(reg: Registry, grid: int, n_records: int = 0, n_windows: int = 1) -> int:
+    from . import workspace_bytes_n
+    return workspace_bytes_n(reg, n_records, n_windows, grid)
 
 
-def tuning_workspace(reg: Registry, device=None):
+def tuning_workspace(reg: Registry, device=None, n_records: int = 0, n_windows: int = 1):
     """A workspace large enough for every tuning candidate, so all of them
-    are timed on the partial-table merge that the tuned launch uses."""
+    are timed on the merge that the tuned launch uses (the partial tables, or,
+    for a table beyond LDS, the spilled rows of n_records records)."""
     from . import make_workspace
-    return make_workspace(reg, max(candidate_grids(reg)), device=device)
+    return make_workspace(reg, max(candidate_grids(reg)), device=device, n_records=n_records, n_windows=n_windows)
 
 
 def _load(path: str) -> Dict[str, dict]:
