@@ -19,7 +19,8 @@ Beside the headline line, the other forms:
   20,000 sites (lookup structure and tables beyond LDS), autotuned and
   graph-replayed;
 * median: the same plain and 8-window batched steps with the rate
-  histograms filled by the classify pass, then the lower medians and the
+  histograms filled by the classify pass (keys staged in the workspace and
+  counted by the histogram kernels), then the lower medians and the
   two-window warning (the paper's warning criterion);
 * filtered: the plain step with the paper's exclusion filters on (average
   packet size >= 100 B, >= 1,000 packets, >= 5 s), the thresholds being this
@@ -377,11 +378,16 @@ def main():
     med1 = torch.empty(2 * n_sites, dtype=torch.int32, device=dev)
     mflags1 = torch.empty(n_sites, dtype=torch.uint8, device=dev)
 
+    # a workspace that also holds the staged histogram keys (histogram kernels
+    # instead of the LDS cache, device atomics and the zeroing pass)
+    kw_h = dict(kw, workspace=None if args.no_workspace else
+                gnm.make_workspace(reg, args.grid_blocks, device=dev, n_records=n_win, hist=True))
+
     def median_step(k, ev=None):
-        # classify call with histograms (zeroing + classify + merge), then medians + warning
+        # classify call with histograms (classify, merge, histogram kernels), then medians + warning
         if ev is not None:
             ev[0].record()
-        gnm.classify_aggregate(reg, structs[k], acc, rate_hist=hist1, **kw)
+        gnm.classify_aggregate(reg, structs[k], acc, rate_hist=hist1, **kw_h)
         if ev is not None:
             ev[1].record()
         gnm.median_flags(reg, hist1, 1, mflags1, median_bucket=med1)
@@ -408,11 +414,13 @@ def main():
     hist_b = gnm.make_rate_hist(reg, nb, device=dev)
     med_b = torch.empty(nb * 2 * n_sites, dtype=torch.int32, device=dev)
     mflags_b = torch.empty(nb * n_sites, dtype=torch.uint8, device=dev)
+    kw_hb = dict(kw, workspace=None if args.no_workspace else
+                 gnm.make_workspace(reg, args.grid_blocks, device=dev, n_records=big.n, n_windows=nb, hist=True))
 
     def median_batched(ev=None):
         if ev is not None:
             ev[0].record()
-        gnm.classify_aggregate(reg, bstruct, acc_b, window_offsets=off_dev, n_windows=nb, rate_hist=hist_b, **kw)
+        gnm.classify_aggregate(reg, bstruct, acc_b, window_offsets=off_dev, n_windows=nb, rate_hist=hist_b, **kw_hb)
         if ev is not None:
             ev[1].record()
         gnm.median_flags(reg, hist_b, nb, mflags_b, median_bucket=med_b)
@@ -435,7 +443,7 @@ def main():
     log("median (batched %d x 10M): %.3f ms/step; classify+histogram call %.4f ms, medians %.4f ms" %
         (nb, wall_mb / args.batched_steps * 1e3, mbk, mbm))
     # bytes each step must move at the least: the records' read fields, the
-    # histograms written once (zeroing) and read once (medians)
+    # histograms written once and read once (medians)
     m_alg = n_win * ALG_BYTES_PER_RECORD + 2 * hist_bytes
     forms["median"] = {
         "records_per_s": args.steps * n_win / wall_m, "step_ms": wall_m / args.steps * 1e3,
@@ -450,7 +458,7 @@ def main():
         "step_gb_s": (big.n * ALG_BYTES_PER_RECORD + 2 * nb * hist_bytes) / ((mbk + mbm) * 1e-3) / 1e9,
         "launch": "one persistent classify launch with histograms over %d windows, then medians and the "
                   "two-window warning over them" % nb}
-    del hist_b
+    del hist_b, kw_hb
 
     # ---------------------------------------------------------------- NetFlow v5 ingest
     d_v5 = torch.from_numpy(v5_buf).to(dev)

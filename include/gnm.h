@@ -164,8 +164,9 @@ typedef struct {
                                   maximum (larger values are clamped to it, since a table row counts
                                   flows and bulk flows in 32 bits each).  Only tests lower it, to
                                   exercise the mid-launch flush; results do not depend on it */
-  void *workspace;             /* optional DEVICE scratch, 16-byte aligned; see below */
-  uint64_t workspace_bytes;    /* its size; >= gnm_workspace_bytes(reg, grid_blocks) to be used */
+  void *workspace;             /* optional DEVICE scratch, 16-byte aligned (256-byte for spilled tables and
+                                  staged histograms); see below */
+  uint64_t workspace_bytes;    /* its size: gnm_workspace_bytes, _n or _hist (below) say what each part needs */
   uint32_t *rate_hist;         /* optional DEVICE rate histograms (layout above), 16-byte aligned: NULL = none;
                                   else filled by the same pass (zeroed first unless GNM_ACCUMULATE) */
   /* Exclusion filters (§III.B.2, TransRate Kernel: reverse-direction flows of
@@ -300,6 +301,28 @@ uint64_t gnm_workspace_bytes_n(const gnm_registry *reg, uint64_t n_records, uint
                                uint32_t grid_blocks);
 
 /*
+ * gnm_workspace_bytes_hist — size of the classify workspace for a call with
+ * rate histograms (gnm_params.rate_hist) over n_records records in n_windows
+ * windows on grid_blocks workgroups (0 = the automatic launch; the size fits
+ * every automatic launch of up to n_records records): the tables' part,
+ * gnm_workspace_bytes_n rounded up to 256 bytes, then the histograms' part.
+ * With it (and a 256-byte aligned workspace) the classify kernel stages one
+ * 4-byte key (the flow's row over all windows, its rate bucket) per bulk
+ * flow of a registered site instead of counting it; the keys are ordered by
+ * ranges of rows (twice 4 bytes per record, plus a partition count per
+ * workgroup) and one workgroup per range (or per slice of 16,384 keys of a
+ * range) counts them in LDS and writes the range's rows of rate_hist whole,
+ * so no zeroing pass and no device-scope atomics are needed except for the
+ * rows of ranges holding several slices.  Results are the same bit for bit.
+ * Calls whose n_windows * 2 * n_sites rows pass 65,536, calls of 2^32 records
+ * or more, and calls whose workspace is smaller keep the LDS cache and
+ * device-scope atomics; for the first two this returns the tables' part
+ * alone.  0 for a NULL registry or n_windows = 0.
+ */
+uint64_t gnm_workspace_bytes_hist(const gnm_registry *reg, uint64_t n_records, uint32_t n_windows,
+                                  uint32_t grid_blocks);
+
+/*
  * gnm_host_work_bytes — size of the work buffer of a gnm_host_table for a
  * classify call over n_records records on grid_blocks workgroups (0 = the
  * automatic launch; it fits every automatic launch of up to n_records
@@ -328,13 +351,16 @@ uint64_t gnm_host_work_bytes(const gnm_registry *reg, uint64_t n_records, uint32
  *                   window-major.  Initialised by the call unless
  *                   p->flags has GNM_ACCUMULATE (then added into).
  *   stream          the caller's stream.
- * Enqueues up to four kernels: table initialisation (skipped when
- * accumulating, or when a single window is rebuilt entirely by the reduce
- * step), histogram zeroing (p->rate_hist set and not accumulating), the
- * classify kernel, and (with a usable p->workspace) the reduce kernel.  With
- * p->rate_hist, each bulk flow of a registered site also adds one to its
- * row's histogram with a device-scope 32-bit atomic; the caller owns the
- * histogram memory (n_windows * 2 * n_sites * GNM_RATE_BUCKETS * 4 bytes).
+ * Enqueues table initialisation (skipped when accumulating, or when a single
+ * window is rebuilt entirely by the reduce step), histogram zeroing
+ * (p->rate_hist set, not accumulating, and no workspace for the histograms),
+ * the classify kernel, and (with a usable p->workspace) the reduce kernel.
+ * With p->rate_hist, each bulk flow of a registered site also adds one to
+ * its row's histogram: through an LDS cache and device-scope 32-bit atomics,
+ * or, with a workspace of gnm_workspace_bytes_hist, as a staged key, which
+ * four more kernels order by row and count (see gnm_workspace_bytes_hist);
+ * the caller owns the histogram memory (n_windows * 2 * n_sites *
+ * GNM_RATE_BUCKETS * 4 bytes).
  * With p->hosts, the classify kernel also stages each such flow (host key,
  * bytes, rate) in p->hosts->work, and four kernels follow: partition counts
  * by a hash of the key, their scan, the scatter into partition order, and one

@@ -36,7 +36,8 @@ RECORD_FIELDS = {"src_ip": 4, "dst_ip": 4, "bytes": 8, "packets": 4, "first_ms":
 
 # symbols declared in include/gnm.h
 EXPORTS = ("gnm_registry_build", "gnm_registry_free", "gnm_registry_info_get", "gnm_acc_rows",
-           "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_workspace_bytes_n", "gnm_host_work_bytes", "gnm_classify_aggregate",
+           "gnm_registry_lookup_host", "gnm_params_default", "gnm_workspace_bytes", "gnm_workspace_bytes_n", "gnm_workspace_bytes_hist",
+           "gnm_host_work_bytes", "gnm_classify_aggregate",
            "gnm_classify_flag", "gnm_classify_flag_static", "gnm_static_scratch_bytes", "gnm_flag_suboptimal", "gnm_median_flags", "gnm_graph_create", "gnm_graph_launch", "gnm_graph_free", "gnm_autotune",
            "gnm_netflow_v5_workspace_bytes", "gnm_netflow_v5_decode",
            "gnm_strerror", "gnm_last_error", "gnm_version")
@@ -191,6 +192,8 @@ def lib():
         L.gnm_workspace_bytes.restype = ctypes.c_uint64
         L.gnm_workspace_bytes_n.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
         L.gnm_workspace_bytes_n.restype = ctypes.c_uint64
+        L.gnm_workspace_bytes_hist.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.gnm_workspace_bytes_hist.restype = ctypes.c_uint64
         L.gnm_host_work_bytes.argtypes = [P, ctypes.c_uint64, ctypes.c_uint32]
         L.gnm_host_work_bytes.restype = ctypes.c_uint64
         L.gnm_classify_aggregate.argtypes = [P, ctypes.POINTER(RecordsC), P, ctypes.c_uint32,
@@ -399,14 +402,26 @@ def workspace_bytes_n(reg: Registry, n_records: int, n_windows: int = 1, grid_bl
     return int(lib().gnm_workspace_bytes_n(reg.handle, int(n_records), int(n_windows), int(grid_blocks)))
 
 
+def workspace_bytes_hist(reg: Registry, n_records: int, n_windows: int = 1, grid_blocks: int = 0) -> int:
+    """gnm_workspace_bytes_hist: scratch size for a call with rate histograms, whose keys it also holds."""
+    return int(lib().gnm_workspace_bytes_hist(reg.handle, int(n_records), int(n_windows), int(grid_blocks)))
+
+
 def make_workspace(reg: Registry, grid_blocks: int = 0, device=None, n_records: Optional[int] = None,
-                   n_windows: int = 1):
+                   n_windows: int = 1, hist: bool = False):
     """A device byte tensor of gnm_workspace_bytes(reg, grid_blocks) bytes, or, with
     n_records, of gnm_workspace_bytes_n (which also holds the spilled rows of a
-    table too large for LDS); 256-byte aligned (torch's allocations are)."""
+    table too large for LDS), or with hist as well, of gnm_workspace_bytes_hist
+    (which also holds the staged histogram keys); 256-byte aligned (torch's
+    allocations are)."""
     import torch
-    nb = workspace_bytes(reg, grid_blocks) if n_records is None else \
-        workspace_bytes_n(reg, n_records, n_windows, grid_blocks)
+    if hist and n_records is None:
+        raise ValueError("a workspace for staged histograms needs n_records")
+    if hist:
+        nb = workspace_bytes_hist(reg, n_records, n_windows, grid_blocks)
+    else:
+        nb = workspace_bytes(reg, grid_blocks) if n_records is None else \
+            workspace_bytes_n(reg, n_records, n_windows, grid_blocks)
     t = torch.empty(max(nb, 1), dtype=torch.uint8, device=device if device is not None else "cuda")
     if t.data_ptr() % 256:
         raise RuntimeError("device allocation not 256-byte aligned")

@@ -10,9 +10,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgnm.so")
-SOURCES = ["registry.cpp", "kernels.hip", "hosts.hip", "table.hip", "forms.cpp", "ingest.hip"]
+SOURCES = ["registry.cpp", "kernels.hip", "hist.hip", "hosts.hip", "table.hip", "forms.cpp", "ingest.hip"]
 HEADERS = [os.path.join(INCLUDE, "gnm.h"), os.path.join(CSRC, "gnm_internal.h"),
-           os.path.join(CSRC, "registry.h"), os.path.join(CSRC, "gnm_device.h"), os.path.join(CSRC, "hosts.h"),
+           os.path.join(CSRC, "registry.h"), os.path.join(CSRC, "gnm_device.h"), os.path.join(CSRC, "hist.h"),
+           os.path.join(CSRC, "hosts.h"),
            os.path.join(CSRC, "partition.h"), os.path.join(CSRC, "table.h")]
 
 # Packed FP32 instructions are kept off for every device pass.

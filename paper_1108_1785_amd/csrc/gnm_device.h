@@ -1,5 +1,5 @@
-// Device helpers shared by the classify kernels (kernels.hip) and the per-host
-// statistics kernels (hosts.hip).
+// Device helpers shared by the classify kernels (kernels.hip), the histogram
+// kernels (hist.hip) and the per-host statistics kernels (hosts.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,6 +9,7 @@
 namespace gnm {
 
 typedef unsigned long long u64;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kBuckets = 10001;  // rate histogram: 10 kbps buckets, the last for >= 100 Mbps
 constexpr uint32_t kBucketBps = 10000;

@@ -56,6 +56,7 @@ typedef u64 u64x2 __attribute__((ext_vector_type(2)));
 // entries of a host land in one partition.
 struct HostPart {
   uint32_t pbits;
+  static constexpr bool kTotalsHook = false;
   static __device__ __forceinline__ uint32_t part(const HostEntry &e, const HostPart &t) {
     return (uint32_t)(mix64(e.key) >> (64u - t.pbits));
   }
@@ -338,7 +339,8 @@ int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, hi
     const uint32_t P = pa.nparts;
     hipLaunchKernelGGL((part_count_kernel<HostEntry, HostPart>), dim3((uint32_t)grid), dim3(kPartThreads), P * 4u,
                        stream, pa, hp);
-    hipLaunchKernelGGL((part_scan_kernel<HostEntry>), dim3(P / 64u), dim3(64 * kPartScanWaves), 0, stream, pa);
+    hipLaunchKernelGGL((part_scan_kernel<HostEntry, HostPart>), dim3(P / 64u), dim3(64 * kPartScanWaves), 0, stream,
+                       pa, hp);
     hipLaunchKernelGGL((part_scatter_kernel<HostEntry, HostPart>), dim3((uint32_t)grid), dim3(kPartThreads),
                        P * 4u, stream, pa, hp);
     hipLaunchKernelGGL(host_reduce_kernel, dim3(P), dim3(kHostThreads), 0, stream, q);

@@ -41,13 +41,13 @@
 #include <string>
 
 #include "gnm_device.h"
+#include "hist.h"
 #include "hosts.h"
 #include "registry.h"
 #include "table.h"
 
 namespace gnm {
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 // Pointers into the global address space (not flat).
 typedef __attribute__((address_space(1))) const uint32_t gu32;
@@ -103,7 +103,13 @@ struct ClassifyArgs {
   TableEntry *ts_entry;               // spilled rows (a table beyond LDS, with a workspace; NULL: device
   uint32_t *ts_count;                 //   atomics): workgroup b's entries at [s_b, s_b + ts_count[b]),
   uint32_t ts_extra;                  //   s_b = lo_b + b * ts_extra, room for hi_b - lo_b + ts_extra
-  uint32_t lds_off_ctr;               // LDS words: the workgroup's staging cursors (hosts, spilled rows)
+  uint32_t *ks_key;                   // staged histogram keys (FEAT & kFeatHist, with a workspace; NULL: the
+  uint32_t *ks_count;                 //   LDS cache and device atomics): workgroup b's at [lo_b, lo_b + ks_count[b])
+  uint32_t *kp_hist;                  // staged keys counted per partition here: [grid][kp_parts] (NULL: not here)
+  unsigned long long *kp_over;        //   a word workgroup 0 clears (the histogram kernels' overflow slices)
+  uint32_t kp_shift, kp_parts;        //   partition of a key: key >> (14 + kp_shift), kp_parts of them
+  uint32_t lds_off_kp;                //   LDS counters
+  uint32_t lds_off_ctr;               // LDS words: the workgroup's staging cursors (hosts, spilled rows, keys)
   uint32_t filters;                   // any exclusion filter set
   uint32_t min_avg_packet_bytes, min_packets, min_duration_ms;
   LocalRanges local;
@@ -326,7 +332,12 @@ struct Lds {
   HostEntry *se;    // per-host staging: this workgroup's range
   uint32_t *tcur;   // spilled rows: partial rows this workgroup has staged
   TableEntry *te;   // spilled rows: this workgroup's range (NULL: misses and flushes use device atomics)
+  uint32_t *kcur;   // staged histogram keys: keys this workgroup has staged (without per-host staging)
+  uint32_t *ke;     // staged histogram keys: this workgroup's range (NULL: the histogram cache)
+  uint32_t *kp;     // staged histogram keys per partition (NULL: counted by the histogram kernels)
+  uint32_t kshift;  // partition of a key: key >> (14 + kshift)
   uint32_t win;     // window of the current segment
+  uint32_t kbase;   // histogram row of the current segment's window: win * hist_rows
 };
 
 // Staging code of a record whose row lives in an LDS cache slot.
@@ -701,13 +712,14 @@ __device__ __forceinline__ void classify_tile(const Addr<R> &t, const ClassifyAr
   for (int k = 0; k < R; ++k) row[k] = one[k] ? 2u * site[k] + (inbound[k] ? 0u : 1u) : rows - 1u;
 }
 
-// Per-host staging of a tile: the wave's entries for all R record slots are
-// reserved with one LDS atomic before the rates are computed (the bulk test
-// and the row decide which records have one), so each entry can be written
-// as soon as its rate is known.  hb[k]: the wave's lanes with an entry in
-// slot k; returns the first entry of slot 0.  Called by the whole wave.
+// Per-host (or histogram key) staging of a tile: the wave's entries for all
+// R record slots are reserved with one LDS atomic on `cursor` before the
+// rates are computed (the bulk test and the row decide which records have
+// one), so each entry can be written as soon as its rate is known.  hb[k]:
+// the wave's lanes with an entry in slot k; returns the first entry of slot
+// 0.  Called by the whole wave.
 template <int R>
-__device__ __forceinline__ uint32_t reserve_hosts(const Lds &L, const bool (&want)[R], uint64_t (&hb)[R]) {
+__device__ __forceinline__ uint32_t reserve_hosts(uint32_t *cursor, const bool (&want)[R], uint64_t (&hb)[R]) {
   uint32_t total = 0;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
@@ -716,7 +728,7 @@ __device__ __forceinline__ uint32_t reserve_hosts(const Lds &L, const bool (&wan
   }
   if (total == 0u) return 0u;
   uint32_t base = 0;
-  if (__lane_id() == (uint32_t)__builtin_ctzll(__builtin_amdgcn_read_exec())) base = atomicAdd(L.hcur, total);
+  if (__lane_id() == (uint32_t)__builtin_ctzll(__builtin_amdgcn_read_exec())) base = atomicAdd(cursor, total);
   return __builtin_amdgcn_readfirstlane(base);
 }
 
@@ -749,16 +761,19 @@ __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t 
     durv[k] = dur;
     bulkv[k] = bulk;
   }
-  // per-host statistics: bulk flows of registered sites (not the "no site"
-  // rows or NODIR), keyed by the remote endpoint (the source of an inbound
-  // flow, the destination of an outbound one)
+  // per-host statistics and staged histogram keys: bulk flows of registered
+  // sites (not the "no site" rows or NODIR); a host is keyed by the remote
+  // endpoint (the source of an inbound flow, the destination of an outbound
+  // one).  With both, one reservation serves the two ranges.
+  constexpr bool HOSTS = (FEAT & kFeatHosts) != 0;
+  const bool kst = (FEAT & kFeatHist) && L.ke != nullptr;
   uint64_t hb[R];
   uint32_t hpos = 0;
-  if (FEAT & kFeatHosts) {
+  if (HOSTS || kst) {
     bool want[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) want[k] = bulkv[k] & (row[k] < a.hist_rows);
-    hpos = reserve_hosts<R>(L, want, hb);
+    hpos = reserve_hosts<R>(HOSTS ? L.hcur : L.kcur, want, hb);
   }
   const uint64_t below = (1ull << __lane_id()) - 1ull;
 #pragma unroll
@@ -783,12 +798,19 @@ __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t 
     if (bulk) {
       if (!miss) add_rate<ACC_LDS>(L, g_tab, code, rate);
       // count in the row's histogram: registered sites only
-      if ((FEAT & kFeatHist) && row[k] < a.hist_rows) hist_add(L, h_tab, row[k], rate_bucket(rate));
-      if ((FEAT & kFeatHosts) && row[k] < a.hist_rows)
+      if ((FEAT & kFeatHist) && row[k] < a.hist_rows) {
+        if (kst) {
+          const uint32_t grow = L.kbase + row[k];
+          L.ke[hpos + (uint32_t)__builtin_popcountll(hb[k] & below)] = (grow << kHistBucketBits) | rate_bucket(rate);
+          if (L.kp) atomicAdd(&L.kp[grow >> L.kshift], 1u);
+        } else
+          hist_add(L, h_tab, row[k], rate_bucket(rate));
+      }
+      if (HOSTS && row[k] < a.hist_rows)
         stage_host(L, hpos + (uint32_t)__builtin_popcountll(hb[k] & below),
                    ((uint64_t)((row[k] & 1u) ? t.d[k] : t.s[k]) << 32) | row[k], r.b[k], rate);
     }
-    if (FEAT & kFeatHosts) hpos += (uint32_t)__builtin_popcountll(hb[k]);
+    if (HOSTS || kst) hpos += (uint32_t)__builtin_popcountll(hb[k]);
   }
 }
 
@@ -869,10 +891,16 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   for (uint32_t i = tid; i < 2u * hslots; i += kThreads) s_htags[i] = 0u;  // tags, then counts
   constexpr bool HOSTS = (FEAT & kFeatHosts) != 0;
   const bool spill = !ACC_LDS && a.ts_entry != nullptr;
-  uint32_t *s_hcur = (uint32_t *)(lds + a.lds_off_ctr), *s_tcur = s_hcur + 1;
-  if ((HOSTS || spill) && tid == 0) {
-    s_hcur[0] = 0u;
-    s_tcur[0] = 0u;
+  const bool kst = HIST && a.ks_key != nullptr;
+  // cursors: per-host entries, spilled rows, the spilled-row flush's claimed
+  // slots, histogram keys
+  uint32_t *s_hcur = (uint32_t *)(lds + a.lds_off_ctr), *s_tcur = s_hcur + 1, *s_kcur = s_hcur + 3;
+  if ((HOSTS || spill || kst) && tid < 4u) s_hcur[tid] = 0u;
+  uint32_t *s_kp = (uint32_t *)(lds + a.lds_off_kp);
+  const bool kcount = kst && a.kp_hist != nullptr;
+  if (kcount) {
+    for (uint32_t i = tid; i < a.kp_parts; i += kThreads) s_kp[i] = 0u;
+    if (blockIdx.x == 0 && tid == 0) *a.kp_over = 0ull;
   }
   __syncthreads();
   // this workgroup's balanced slice of all records
@@ -880,7 +908,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
   const uint64_t hi = (uint64_t)(blockIdx.x + 1) * a.n / gridDim.x;
   Lds L{s_root, s_lines, s_acc, s_tags, slots, s_htags, s_htags + hslots, hslots, s_hcur,
         HOSTS ? a.hs_entry + lo : nullptr, s_tcur, spill ? a.ts_entry + lo + (uint64_t)blockIdx.x * a.ts_extra : nullptr,
-        0u};
+        s_kcur, kst ? a.ks_key + lo : nullptr, kcount ? s_kp : nullptr, a.kp_shift, 0u, 0u};
   // spilled rows: the entries this workgroup's range holds
   const uint32_t t_cap = (uint32_t)(hi - lo) + a.ts_extra;
   if (lo == hi) {
@@ -891,6 +919,9 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     }
     if (HOSTS && tid == 0) a.hs_count[blockIdx.x] = 0u;
     if (spill && tid == 0) a.ts_count[blockIdx.x] = 0u;
+    if (kst && tid == 0) a.ks_count[blockIdx.x] = 0u;
+    if (kcount)
+      for (uint32_t j = tid; j < a.kp_parts; j += kThreads) a.kp_hist[(uint64_t)blockIdx.x * a.kp_parts + j] = 0u;
     return;
   }
   uint64_t i = lo;
@@ -901,6 +932,7 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     if (seg_end - i > a.flush_records) seg_end = i + a.flush_records;
     u64 *g_tab = a.acc + (uint64_t)w * rows * 8u;
     L.win = w;
+    L.kbase = w * a.hist_rows;
     uint32_t *h_tab = HIST ? a.hist + (uint64_t)w * a.hist_rows * kBuckets : nullptr;
 
     if (VEC) {
@@ -930,10 +962,14 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     if (HIST && hslots) flush_hist(L, h_tab);
     i = seg_end;
   }
-  if (HOSTS || spill) {
+  if (HOSTS || spill || kst) {
     __syncthreads();
     if (HOSTS && tid == 0) a.hs_count[blockIdx.x] = *s_hcur;
     if (spill && tid == 0) a.ts_count[blockIdx.x] = *s_tcur;
+    // with per-host staging the keys share its cursor
+    if (kst && tid == 0) a.ks_count[blockIdx.x] = HOSTS ? *s_hcur : *s_kcur;
+    if (kcount)
+      for (uint32_t j = tid; j < a.kp_parts; j += kThreads) a.kp_hist[(uint64_t)blockIdx.x * a.kp_parts + j] = s_kp[j];
   }
 }
 
@@ -1363,6 +1399,16 @@ extern "C" uint64_t gnm_workspace_bytes_n(const gnm_registry *reg, uint64_t n_re
   return table_spill_bytes(n_records, grid, n_windows, (uint32_t)reg->rows(), reg->cache_slots);
 }
 
+extern "C" uint64_t gnm_workspace_bytes_hist(const gnm_registry *reg, uint64_t n_records, uint32_t n_windows,
+                                             uint32_t grid_blocks) {
+  if (!reg || n_windows == 0) return 0;
+  const uint64_t grid = grid_blocks ? grid_blocks : (uint64_t)device_cus(reg->device) * blocks_per_cu(reg);
+  const uint64_t tables = (gnm_workspace_bytes_n(reg, n_records, n_windows, grid_blocks) + 255u) & ~255ull;
+  const uint32_t hist_rows = 2u * reg->n_sites;
+  if (!hist_stage_fits(n_records, n_windows, hist_rows)) return tables;
+  return tables + hist_work_bytes(n_records, grid, n_windows, hist_rows);
+}
+
 extern "C" uint64_t gnm_workspace_bytes(const gnm_registry *reg, uint32_t grid_blocks) {
   if (!reg) return 0;
   const uint64_t grid = grid_blocks ? grid_blocks : (uint64_t)device_cus(reg->device) * blocks_per_cu(reg);
@@ -1462,19 +1508,6 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     a.hs_entry = st.entry;
     a.hs_count = st.count;
   }
-  uint32_t lds_launch = reg->lds_bytes;
-  if (p.rate_hist) {
-    // the histogram cache takes the LDS the registry leaves free, within the
-    // budget that keeps the registry's workgroups per CU
-    const uint32_t off = (reg->lds_bytes + 15u) & ~15u;
-    const uint32_t budget = (reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax) - kLdsReserve;
-    uint32_t hs = budget > off ? (budget - off) / 8u : 0u;
-    hs = (hs < kHistSlotsMax ? hs : kHistSlotsMax) & ~3u;
-    if (hs < 64u) hs = 0;
-    a.lds_off_hist = off;
-    a.hist_slots = hs;
-    lds_launch = off + hs * 8u;
-  }
   // a table beyond LDS with a workspace that holds its spilled rows: the
   // misses of the row cache and its flushes are staged and merged by the
   // table kernels instead of device-scope atomics
@@ -1487,7 +1520,51 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     a.ts_count = ts.count;
     a.ts_extra = (uint32_t)table_extra(reg->cache_slots);
   }
-  if (ht || spill) {
+  // histograms with a workspace that also holds their keys, after what the
+  // tables use of it: staged keys and the histogram kernels instead of the
+  // LDS cache, device-scope atomics and the zeroing pass
+  char *hist_work = nullptr;
+  HistStage ks{};
+  if (p.rate_hist && rec->n > 0 && p.workspace && ((uintptr_t)p.workspace & 255u) == 0 &&
+      hist_stage_fits(rec->n, n_windows, a.hist_rows)) {
+    const uint64_t used = spill ? table_spill_bytes(rec->n, grid, n_windows, (uint32_t)rows, reg->cache_slots)
+                                : (use_ws ? partial_bytes(reg, grid) : 0u);
+    const uint64_t off = (used + 255u) & ~255ull;
+    if (p.workspace_bytes >= off + hist_work_bytes(rec->n, grid, n_windows, a.hist_rows)) {
+      hist_work = (char *)p.workspace + off;
+      ks = hist_stage(hist_work, rec->n, grid, n_windows, a.hist_rows);
+      a.ks_key = ks.key;
+      a.ks_count = ks.count;
+    }
+  }
+  uint32_t lds_launch = reg->lds_bytes;
+  if (p.rate_hist && !hist_work) {
+    // the histogram cache takes the LDS the registry leaves free, within the
+    // budget that keeps the registry's workgroups per CU
+    const uint32_t off = (reg->lds_bytes + 15u) & ~15u;
+    const uint32_t budget = (reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax) - kLdsReserve;
+    uint32_t hs = budget > off ? (budget - off) / 8u : 0u;
+    hs = (hs < kHistSlotsMax ? hs : kHistSlotsMax) & ~3u;
+    if (hs < 64u) hs = 0;
+    a.lds_off_hist = off;
+    a.hist_slots = hs;
+    lds_launch = off + hs * 8u;
+  }
+  if (hist_work) {
+    // the keys' partition counts in LDS too, when they fit that budget
+    // (otherwise the count kernel counts them)
+    const uint32_t off = (lds_launch + 15u) & ~15u;
+    const uint32_t budget = (reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax) - kLdsReserve;
+    if (off + 4u * ks.nparts <= budget) {
+      a.kp_hist = ks.phist;
+      a.kp_over = ks.over;
+      a.kp_shift = ks.shift;
+      a.kp_parts = ks.nparts;
+      a.lds_off_kp = off;
+      lds_launch = off + 4u * ks.nparts;
+    }
+  }
+  if (ht || spill || hist_work) {
     // the staging cursors: words in the bytes every LDS plan leaves free
     a.lds_off_ctr = (lds_launch + 15u) & ~15u;
     lds_launch = a.lds_off_ctr + 16u;
@@ -1511,6 +1588,10 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     e = allow_lds(fn, (int)feat * 16 + shape * 4 + (reg->lines_in_lds ? 2 : 0) + (reg->acc_in_lds ? 1 : 0), dev);
     if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
   }
+  if (hist_work) {
+    e = hist_prepare(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute (histograms)");
+  }
   if (!launch) return GNM_OK;
 
   if (!(p.flags & GNM_ACCUMULATE) && !overwrite) {
@@ -1520,7 +1601,7 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "init launch");
   }
-  if (p.rate_hist && !(p.flags & GNM_ACCUMULATE)) {
+  if (p.rate_hist && !(p.flags & GNM_ACCUMULATE) && !hist_work) {
     const uint64_t quads = (hist_words + 3u) / 4u;
     const uint64_t cap = (uint64_t)device_cus(dev) * 64u;
     const uint64_t blocks = (quads + 255u) / 256u < cap ? (quads + 255u) / 256u : cap;
@@ -1571,6 +1652,11 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
   } else {
     const int rc = flag_launch();
+    if (rc != GNM_OK) return rc;
+  }
+  if (hist_work) {
+    const int rc = hist_pipeline_launch(hist_work, rec->n, grid, n_windows, a.hist_rows, p.rate_hist,
+                                        (p.flags & GNM_ACCUMULATE) != 0, a.kp_hist != nullptr, stream);
     if (rc != GNM_OK) return rc;
   }
   return count_hosts();

@@ -10,8 +10,15 @@
 //                        and the partition totals;
 //   part_scatter_kernel  every entry to its place (partition base, the
 //                        workgroup's offset, an LDS cursor).
-// Entry types provide `static uint32_t part(const Entry &, const Traits &)`
-// through the Traits template argument and are copied as 16-byte words.
+// The Traits template argument provides `static uint32_t part(const Entry &,
+// const Traits &)` and `static constexpr bool kTotalsHook`; with the hook,
+// every scan workgroup also calls `Traits::totals(tot, p0, t)` with all its
+// threads once the totals tot[0..64) of partitions p0 .. p0 + 63 are in LDS,
+// and every scatter workgroup b of `grid` calls `Traits::scatter_share(tot,
+// P, t, b, grid)` with all the totals in LDS.
+// Entries of 16-byte multiples are copied as 16-byte words, smaller ones
+// whole.  The count kernel can be left out when the producer writes the
+// count matrix itself.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,17 +54,6 @@ __device__ __forceinline__ uint64_t part_stage_lo(uint32_t b, uint64_t n, uint32
   return (uint64_t)b * n / grid + (uint64_t)b * extra;
 }
 
-template <class E>
-__device__ __forceinline__ void copy_entry(E *dst, const E *src) {
-  static_assert(sizeof(E) % 16 == 0, "entries are copied as 16-byte words");
-  typedef u64 u64x2p __attribute__((ext_vector_type(2)));
-  u64x2p w[sizeof(E) / 16];
-#pragma unroll
-  for (uint32_t j = 0; j < sizeof(E) / 16; ++j) w[j] = ((const u64x2p *)src)[j];
-#pragma unroll
-  for (uint32_t j = 0; j < sizeof(E) / 16; ++j) ((u64x2p *)dst)[j] = w[j];
-}
-
 // Partition counts of classify workgroup b's entries (dynamic LDS: nparts
 // counters).  Workgroup 0 also clears the caller's counter words.
 template <class E, class T>
@@ -91,9 +87,10 @@ __global__ __launch_bounds__(kPartThreads) void part_count_kernel(const PartArgs
 // sixteenth of the classify workgroups, sum their counts (8 loads in flight
 // per lane), meet in LDS, and then rewrite the counts as exclusive offsets.
 // Also the partition totals, and the number of staged entries.
-template <class E>
-__global__ __launch_bounds__(64 * kPartScanWaves) void part_scan_kernel(const PartArgs<E> q) {
+template <class E, class T>
+__global__ __launch_bounds__(64 * kPartScanWaves) void part_scan_kernel(const PartArgs<E> q, const T t) {
   __shared__ uint32_t part[kPartScanWaves][64];
+  __shared__ uint32_t tot[64];
   const uint32_t P = q.nparts, lane = threadIdx.x % 64u, w = threadIdx.x / 64u;
   const uint32_t p = blockIdx.x * 64u + lane;
   const uint32_t chunk = (q.grid + kPartScanWaves - 1u) / kPartScanWaves;
@@ -126,12 +123,17 @@ __global__ __launch_bounds__(64 * kPartScanWaves) void part_scan_kernel(const Pa
   }
   if (w == 0) {
     q.ptotal[p] = total;
+    tot[lane] = total;
     if (q.staged) {
-      u64 t = total;
+      u64 c = total;
 #pragma unroll
-      for (uint32_t o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-      if (lane == 0 && t) __hip_atomic_fetch_add(q.staged, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (uint32_t o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+      if (lane == 0 && c) __hip_atomic_fetch_add(q.staged, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  }
+  if constexpr (T::kTotalsHook) {
+    __syncthreads();
+    T::totals(tot, blockIdx.x * 64u, t);
   }
 }
 
@@ -173,6 +175,7 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(const PartAr
   const uint32_t P = q.nparts, b = blockIdx.x;
   for (uint32_t p = threadIdx.x; p < P; p += kPartThreads) cur[p] = q.ptotal[p];
   __syncthreads();
+  if constexpr (T::kTotalsHook) T::scatter_share(cur, P, t, b, q.grid);
   part_exclusive_scan(cur, P, wsum);
   if (b == 0)
     for (uint32_t p = threadIdx.x; p < P; p += kPartThreads) q.pbase[p] = cur[p];
@@ -181,9 +184,30 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(const PartAr
   __syncthreads();
   const uint64_t lo = part_stage_lo(b, q.n, q.grid, q.extra);
   const uint32_t cnt = q.scount[b];
+  if constexpr (sizeof(E) % 16 != 0) {
+    // small entries: kPartUnroll per lane in flight, copied whole
+    for (uint32_t i0 = 0; i0 < cnt; i0 += kPartUnroll * kPartThreads) {
+      E v[kPartUnroll];
+      uint32_t pos[kPartUnroll];
+#pragma unroll
+      for (uint32_t j = 0; j < kPartUnroll; ++j) {
+        const uint32_t i = i0 + j * kPartThreads + threadIdx.x;
+        if (i < cnt) v[j] = q.stage[lo + i];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kPartUnroll; ++j) {
+        const uint32_t i = i0 + j * kPartThreads + threadIdx.x;
+        pos[j] = i < cnt ? atomicAdd(&cur[T::part(v[j], t)], 1u) : 0u;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kPartUnroll; ++j)
+        if (i0 + j * kPartThreads + threadIdx.x < cnt) q.part[pos[j]] = v[j];
+    }
+    return;
+  }
   // kPartUnroll entries per lane in flight: loaded, then placed, then stored
   typedef u64 u64x2p __attribute__((ext_vector_type(2)));
-  constexpr uint32_t W = sizeof(E) / 16;
+  constexpr uint32_t W = sizeof(E) / 16 ? sizeof(E) / 16 : 1u;
   for (uint32_t i0 = 0; i0 < cnt; i0 += kPartUnroll * kPartThreads) {
     u64x2p v[kPartUnroll][W];
     uint32_t pos[kPartUnroll];

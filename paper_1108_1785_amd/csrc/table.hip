@@ -31,6 +31,7 @@ constexpr uint32_t kTableThreads = 1024;
 // Partition of a partial row: its window's range of kTableTileRows rows.
 struct TablePart {
   uint32_t tiles;  // row ranges per window
+  static constexpr bool kTotalsHook = false;
   static __device__ __forceinline__ uint32_t part(const TableEntry &e, const TablePart &t) {
     return (e.w & kWindowMask) * t.tiles + (e.row & kRowMask) / kTableTileRows;
   }
@@ -185,7 +186,8 @@ int table_merge_launch(void *work, uint64_t n, uint64_t grid, uint32_t n_windows
   const uint32_t P = pa.nparts;
   hipLaunchKernelGGL((part_count_kernel<TableEntry, TablePart>), dim3((uint32_t)grid), dim3(kPartThreads), P * 4u,
                      stream, pa, tp);
-  hipLaunchKernelGGL((part_scan_kernel<TableEntry>), dim3(P / 64u), dim3(64 * kPartScanWaves), 0, stream, pa);
+  hipLaunchKernelGGL((part_scan_kernel<TableEntry, TablePart>), dim3(P / 64u), dim3(64 * kPartScanWaves), 0, stream,
+                     pa, tp);
   hipLaunchKernelGGL((part_scatter_kernel<TableEntry, TablePart>), dim3((uint32_t)grid), dim3(kPartThreads),
                      P * 4u, stream, pa, tp);
   hipLaunchKernelGGL(table_reduce_kernel, dim3(P), dim3(kTableThreads), 0, stream, q);

@@ -119,15 +119,18 @@ def test_spill_accumulate_and_fallback(torch_cuda):
     assert (got3 == exp).all()
 
 
-def test_spill_with_histograms_hosts_filters(torch_cuda):
-    say("case: spilled large-table with histograms, hosts and filters")
+@pytest.mark.parametrize("staged", [False, True])
+def test_spill_with_histograms_hosts_filters(torch_cuda, staged):
+    say("case: spilled large-table with histograms, hosts and filters; staged histogram keys", staged)
     t = _table()
     rec = t["rec"].slice(0, 600_000)
     g = t["g"]
     f = {"min_avg_packet_bytes": 100, "min_packets": 500}
     hist = gnm.make_rate_hist(g)
+    hist.fill_(-1)
     hosts = gnm.HostTable(g, 1 << 18, rec.n, device=DEV)
-    _, got, fl = call(g, rec, rate_hist=hist, hosts=hosts, filters=f)
+    ws = gnm.make_workspace(g, n_records=rec.n, hist=staged)
+    _, got, fl = call(g, rec, rate_hist=hist, hosts=hosts, filters=f, ws=ws)
     exp = expect(t["orc"], rec, filters=f)
     assert (got == exp).all(), diff(got, exp)
     assert (fl == oracle.flags(exp, t["reg"].n_sites)).all()
