@@ -417,9 +417,11 @@ int gnm_classify_flag(const gnm_registry *reg, const gnm_records *rec, const uin
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments, results and errors,
  * except that the workspace is not the caller's: the per-workgroup partial
- * tables live in a static device array of gnm_static_scratch_bytes() bytes
- * (32 MiB) that the library holds on each GPU it runs on until the process
- * ends.  The call itself allocates nothing (no hipMalloc, hipFree or
+ * tables (and, when they fit after them, the spilled rows of a table beyond
+ * LDS or the staged keys of rate histograms; otherwise those use device-scope
+ * atomics, with the same results) live in a static device array of
+ * gnm_static_scratch_bytes() bytes (32 MiB) that the library holds on each
+ * GPU it runs on until the process ends.  The call itself allocates nothing (no hipMalloc, hipFree or
  * allocating library routine); the array's device address is looked up once
  * per device, on the first call made with that device current.
  *   p->workspace    must be NULL (GNM_E_INVAL otherwise).

@@ -1741,10 +1741,12 @@ extern "C" int gnm_median_flags(const gnm_registry *reg, const uint32_t *rate_hi
 namespace gnm {
 
 // Workspace of gnm_classify_flag_static: the per-workgroup partial tables and
-// their window tags, in a file-scope device array.  Each GPU the library runs
-// on holds its own copy until the process ends; every call on that GPU shares
-// it.  Nothing in it needs to start at zero: each classify workgroup writes
-// its whole slot and tag before the reduce kernel reads them.
+// their window tags (and, when they fit, spilled rows or staged histogram
+// keys), in a file-scope device array.  Each GPU the library runs on holds
+// its own copy until the process ends; every call on that GPU shares it.
+// Nothing in it needs to start at zero: each classify workgroup writes its
+// whole slot and tag (and its staging counts) before the kernels after it
+// read them.
 constexpr uint64_t kStaticScratchBytes = 32ull << 20;
 __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
