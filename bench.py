@@ -35,7 +35,8 @@ Beside the headline line, the other forms:
 * served: open-loop Poisson arrivals (200 windows/s, lognormal sizes with
   median 300 k records, capped at 5 M) through the request loop, host records
   copied in over PCIe; p50/p99 latency from scheduled arrival to result;
-  then the same with the record pool already in device memory.
+  then the same with the record pool already in device memory, a burst of
+  2,000 windows, and 1 s runs at rising arrival rates up to the knee.
 
 The CPU oracle is timed on the host's cores on one full window; the GPU
 tables are compared with it bit for bit (plain, batched, sampled batched-256,
@@ -729,6 +730,27 @@ def main():
         log("served (burst of 2000): %.3g records/s, %.1f windows/launch, p50 %.1f ms p99 %.1f ms" %
             (sat["records_per_s"], sat["windows_per_launch"], sat["latency_ms_p50"], sat["latency_ms_p99"]))
         forms["served_saturation"] = sat
+        # capacity: open-loop device-resident runs of 1 s at rising arrival
+        # rates, until the completed rate falls below 90 % of the offered one
+        # or p99 passes 100 ms (the knee).  Same request loop and kernels as
+        # the runs checked against the oracle above; these are not re-checked.
+        if args.served_seconds >= 5:
+            ramp, knee = [], None
+            for k, rate in enumerate((500.0, 1000.0, 2000.0, 4000.0, 8000.0, 16000.0)):
+                rr, _, _, _ = served_run(gnm, serve, reg1, pool_dev, pool.n, 1.0, rate,
+                                         flowgen.SEED_BASE + 410 + k, resident=True, log_every=10.0)
+                ramp.append({x: rr[x] for x in ("arrival_rate_hz", "windows", "records", "records_per_s",
+                                                "offered_records_per_s", "latency_ms_p50", "latency_ms_p99",
+                                                "windows_per_launch", "admission_waits")})
+                log("served ramp %5.0f windows/s: %.3g of %.3g records/s offered, %.1f windows/launch, "
+                    "p50 %.2f ms p99 %.2f ms" % (rate, rr["records_per_s"], rr["offered_records_per_s"],
+                                                   rr["windows_per_launch"], rr["latency_ms_p50"],
+                                                   rr["latency_ms_p99"]))
+                if rr["records_per_s"] < 0.9 * rr["offered_records_per_s"] or rr["latency_ms_p99"] > 100.0:
+                    knee = rate
+                    break
+            forms["served_ramp"] = {"runs": ramp, "knee_arrival_rate_hz": knee,
+                                    "launch": "open-loop Poisson arrivals from device memory, 1 s per rate"}
         del pinned
 
     # ---------------------------------------------------------------- oracle
