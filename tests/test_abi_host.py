@@ -251,3 +251,20 @@ def test_host_work_bytes():
         w1, w2 = gnm.host_work_bytes(reg, n, 256), gnm.host_work_bytes(reg, n, 512)
         assert 64 * n <= w1 < w2 <= 64 * n + 512 * 4 * 16384 + 8 * 16384 + 4096
     assert gnm.lib().gnm_host_work_bytes(None, 100, 1) == 0
+
+
+def test_workspace_bytes_hist():
+    # the tables' part rounded up to 256 bytes, then about 8 bytes per record
+    # (keys staged, then in partition order) plus the count matrix; the tables'
+    # part alone beyond 65,536 rows over all windows
+    reg = gnm.Registry([0x0B000000, 0x0C000000], [8, 8], [0, 1], 2, [0x0A000000], [16], host_only=True)
+    rows = 2 * reg.n_sites
+    for n, nw, grid in ((1, 1, 1), (1000, 3, 7), (10_000_000, 8, 256), (10_000_000, 1, 512)):
+        base = (gnm.workspace_bytes_n(reg, n, nw, grid) + 255) // 256 * 256
+        w = gnm.workspace_bytes_hist(reg, n, nw, grid)
+        parts = (nw * rows + 63) // 64 * 64
+        assert base + 8 * n <= w <= base + 8 * n + 4 * grid * parts + 4 * (n // 16384 + 1) + 16 * 256, (n, nw, grid)
+    big = 65536 // rows + 1  # windows past the staged limit
+    assert gnm.workspace_bytes_hist(reg, 1000, big, 4) == (gnm.workspace_bytes_n(reg, 1000, big, 4) + 255) // 256 * 256
+    assert gnm.lib().gnm_workspace_bytes_hist(None, 100, 1, 1) == 0
+    assert gnm.workspace_bytes_hist(reg, 100, 0, 1) == 0
