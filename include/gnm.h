@@ -168,7 +168,7 @@ typedef struct {
                                   staged histograms); see below */
   uint64_t workspace_bytes;    /* its size: gnm_workspace_bytes, _n or _hist (below) say what each part needs */
   uint32_t *rate_hist;         /* optional DEVICE rate histograms (layout above), 16-byte aligned: NULL = none;
-                                  else filled by the same pass (zeroed first unless GNM_ACCUMULATE) */
+                                  else filled by the same pass (overwritten unless GNM_ACCUMULATE) */
   /* Exclusion filters (§III.B.2, TransRate Kernel: reverse-direction flows of
    * pure ACKs, recognised by a small average packet size, and administrative
    * exchanges of few packets over a short time are left out of the rate
