@@ -30,6 +30,8 @@ struct __attribute__((aligned(32))) HostEntry {
 struct HostStage {
   HostEntry *entry;
   uint32_t *count;  // [grid]: entries staged by each classify workgroup
+  uint32_t *phist;  // [grid][2^pbits]: each classify workgroup's entries per partition
+  uint32_t pbits;   // partition of an entry: mix64(key) >> (64 - pbits)
 };
 
 // log2 of the partition count for a call over n records: the power of two
@@ -42,9 +44,11 @@ uint64_t host_work_bytes(uint64_t n, uint64_t grid);
 // Staging arrays inside a work buffer laid out for (n, grid).
 HostStage host_stage(void *work, uint64_t n, uint64_t grid);
 
-// Enqueue the per-host kernels after the classify kernel: partition counts,
-// their scan, the scatter into partition order and the per-partition
-// reduction into ht's arrays.  With n == 0 only the counters are cleared.
-int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, hipStream_t stream);
+// Enqueue the per-host kernels after the classify kernel: partition counts
+// (left out when the classify kernel counted its entries per partition and
+// cleared ht->counters itself: `counted`), their scan, the scatter into
+// partition order and the per-partition reduction into ht's arrays.  With
+// n == 0 only the counters are cleared.
+int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, bool counted, hipStream_t stream);
 
 }  // namespace gnm

@@ -304,10 +304,11 @@ uint64_t host_work_bytes(uint64_t n, uint64_t grid) { return layout(n, grid).end
 HostStage host_stage(void *work, uint64_t n, uint64_t grid) {
   const PartLayout L = layout(n, grid);
   char *w = (char *)work;
-  return HostStage{(HostEntry *)(w + L.stage), (uint32_t *)(w + L.scount)};
+  return HostStage{(HostEntry *)(w + L.stage), (uint32_t *)(w + L.scount), (uint32_t *)(w + L.phist),
+                   host_part_bits(n)};
 }
 
-int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, hipStream_t stream) {
+int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, bool counted, hipStream_t stream) {
   if (n == 0) {
     hipLaunchKernelGGL(host_clear_kernel, dim3(1), dim3(1), 0, stream, (u64 *)ht->counters);
   } else {
@@ -337,8 +338,9 @@ int host_pipeline_launch(const gnm_host_table *ht, uint64_t n, uint64_t grid, hi
     q.capacity = ht->capacity;
     q.counters = (u64 *)ht->counters;
     const uint32_t P = pa.nparts;
-    hipLaunchKernelGGL((part_count_kernel<HostEntry, HostPart>), dim3((uint32_t)grid), dim3(kPartThreads), P * 4u,
-                       stream, pa, hp);
+    if (!counted)
+      hipLaunchKernelGGL((part_count_kernel<HostEntry, HostPart>), dim3((uint32_t)grid), dim3(kPartThreads), P * 4u,
+                         stream, pa, hp);
     hipLaunchKernelGGL((part_scan_kernel<HostEntry, HostPart>), dim3(P / 64u), dim3(64 * kPartScanWaves), 0, stream,
                        pa, hp);
     hipLaunchKernelGGL((part_scatter_kernel<HostEntry, HostPart>), dim3((uint32_t)grid), dim3(kPartThreads),

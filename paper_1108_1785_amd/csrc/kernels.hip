@@ -109,6 +109,9 @@ struct ClassifyArgs {
   unsigned long long *kp_over;        //   a word workgroup 0 clears (the histogram kernels' overflow slices)
   uint32_t kp_shift, kp_parts;        //   partition of a key: key >> (14 + kp_shift), kp_parts of them
   uint32_t lds_off_kp;                //   LDS counters
+  uint32_t *hp_hist;                  // per-host entries counted per partition here: [grid][2^hp_bits] (NULL: not
+  uint32_t hp_bits, lds_off_hp;       //   here); partition mix64(key) >> (64 - hp_bits); LDS counters
+  unsigned long long *hp_clear;       //   the host table's two counters, cleared by workgroup 0
   uint32_t lds_off_ctr;               // LDS words: the workgroup's staging cursors (hosts, spilled rows, keys)
   uint32_t filters;                   // any exclusion filter set
   uint32_t min_avg_packet_bytes, min_packets, min_duration_ms;
@@ -336,6 +339,8 @@ struct Lds {
   uint32_t *ke;     // staged histogram keys: this workgroup's range (NULL: the histogram cache)
   uint32_t *kp;     // staged histogram keys per partition (NULL: counted by the histogram kernels)
   uint32_t kshift;  // partition of a key: key >> (14 + kshift)
+  uint32_t *hp;     // per-host entries per partition (NULL: counted by the count kernel)
+  uint32_t hpbits;  // partition of a host entry: mix64(key) >> (64 - hpbits)
   uint32_t win;     // window of the current segment
   uint32_t kbase;   // histogram row of the current segment's window: win * hist_rows
 };
@@ -806,9 +811,11 @@ __device__ __forceinline__ void aggregate_tile(const Addr<R> &t, const uint32_t 
         } else
           hist_add(L, h_tab, row[k], rate_bucket(rate));
       }
-      if (HOSTS && row[k] < a.hist_rows)
-        stage_host(L, hpos + (uint32_t)__builtin_popcountll(hb[k] & below),
-                   ((uint64_t)((row[k] & 1u) ? t.d[k] : t.s[k]) << 32) | row[k], r.b[k], rate);
+      if (HOSTS && row[k] < a.hist_rows) {
+        const uint64_t key = ((uint64_t)((row[k] & 1u) ? t.d[k] : t.s[k]) << 32) | row[k];
+        stage_host(L, hpos + (uint32_t)__builtin_popcountll(hb[k] & below), key, r.b[k], rate);
+        if (L.hp) atomicAdd(&L.hp[(uint32_t)(mix64(key) >> (64u - L.hpbits))], 1u);
+      }
     }
     if (HOSTS || kst) hpos += (uint32_t)__builtin_popcountll(hb[k]);
   }
@@ -902,13 +909,21 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     for (uint32_t i = tid; i < a.kp_parts; i += kThreads) s_kp[i] = 0u;
     if (blockIdx.x == 0 && tid == 0) *a.kp_over = 0ull;
   }
+  uint32_t *s_hp = (uint32_t *)(lds + a.lds_off_hp);
+  const bool hcount = HOSTS && a.hp_hist != nullptr;
+  const uint32_t hparts = 1u << a.hp_bits;
+  if (hcount) {
+    for (uint32_t i = tid; i < hparts; i += kThreads) s_hp[i] = 0u;
+    if (blockIdx.x == 0 && tid < 2u) a.hp_clear[tid] = 0ull;
+  }
   __syncthreads();
   // this workgroup's balanced slice of all records
   const uint64_t lo = (uint64_t)blockIdx.x * a.n / gridDim.x;
   const uint64_t hi = (uint64_t)(blockIdx.x + 1) * a.n / gridDim.x;
   Lds L{s_root, s_lines, s_acc, s_tags, slots, s_htags, s_htags + hslots, hslots, s_hcur,
         HOSTS ? a.hs_entry + lo : nullptr, s_tcur, spill ? a.ts_entry + lo + (uint64_t)blockIdx.x * a.ts_extra : nullptr,
-        s_kcur, kst ? a.ks_key + lo : nullptr, kcount ? s_kp : nullptr, a.kp_shift, 0u, 0u};
+        s_kcur, kst ? a.ks_key + lo : nullptr, kcount ? s_kp : nullptr, a.kp_shift, hcount ? s_hp : nullptr, a.hp_bits,
+        0u, 0u};
   // spilled rows: the entries this workgroup's range holds
   const uint32_t t_cap = (uint32_t)(hi - lo) + a.ts_extra;
   if (lo == hi) {
@@ -922,6 +937,8 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     if (kst && tid == 0) a.ks_count[blockIdx.x] = 0u;
     if (kcount)
       for (uint32_t j = tid; j < a.kp_parts; j += kThreads) a.kp_hist[(uint64_t)blockIdx.x * a.kp_parts + j] = 0u;
+    if (hcount)
+      for (uint32_t j = tid; j < hparts; j += kThreads) a.hp_hist[(uint64_t)blockIdx.x * hparts + j] = 0u;
     return;
   }
   uint64_t i = lo;
@@ -970,6 +987,8 @@ __global__ __launch_bounds__(kThreads) void classify_kernel(const ClassifyArgs a
     if (kst && tid == 0) a.ks_count[blockIdx.x] = HOSTS ? *s_hcur : *s_kcur;
     if (kcount)
       for (uint32_t j = tid; j < a.kp_parts; j += kThreads) a.kp_hist[(uint64_t)blockIdx.x * a.kp_parts + j] = s_kp[j];
+    if (hcount)
+      for (uint32_t j = tid; j < hparts; j += kThreads) a.hp_hist[(uint64_t)blockIdx.x * hparts + j] = s_hp[j];
   }
 }
 
@@ -1564,6 +1583,20 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
       lds_launch = off + 4u * ks.nparts;
     }
   }
+  if (ht) {
+    // the per-host entries' partition counts in LDS too, when they fit
+    // (otherwise the count kernel counts them)
+    const HostStage st = host_stage(ht->work, rec->n, grid);
+    const uint32_t off = (lds_launch + 15u) & ~15u;
+    const uint32_t budget = (reg->lds_bytes <= kLdsMax / 2 ? kLdsMax / 2 : kLdsMax) - kLdsReserve;
+    if (rec->n > 0 && off + (4u << st.pbits) <= budget) {
+      a.hp_hist = st.phist;
+      a.hp_bits = st.pbits;
+      a.hp_clear = (unsigned long long *)ht->counters;
+      a.lds_off_hp = off;
+      lds_launch = off + (4u << st.pbits);
+    }
+  }
   if (ht || spill || hist_work) {
     // the staging cursors: words in the bytes every LDS plan leaves free
     a.lds_off_ctr = (lds_launch + 15u) & ~15u;
@@ -1613,7 +1646,7 @@ int classify_impl(const gnm_registry *reg, const gnm_records *rec, const uint64_
   // the per-host kernels, after the classify launch (and on an empty run)
   auto count_hosts = [&]() -> int {
     if (!ht) return GNM_OK;
-    return host_pipeline_launch(ht, rec->n, grid, stream);
+    return host_pipeline_launch(ht, rec->n, grid, a.hp_hist != nullptr, stream);
   };
   // the mean-rate flags, when the reduce kernel does not apply them
   auto flag_launch = [&]() -> int {
